@@ -1,0 +1,299 @@
+"""Pins of the FP64 CPU oracle against what the paper and mathematics fix.
+
+Each test names the invariant it checks; none retypes the oracle's formula:
+library routines (scipy Bessel K, scipy multivariate normal, numpy Cholesky),
+closed-form limits, brute force and finite differences are the references.
+"""
+import numpy as np
+import pytest
+from scipy.special import gamma, kv
+from scipy.stats import multivariate_normal
+
+import oracle as O
+
+TWO_NU = (1, 3, 5, 7)
+
+
+def _theta(beta, s2, t2):
+    return np.r_[np.log(beta), np.log(s2), np.log(t2)]
+
+
+def _data(n, d, seed, beta, s2=1.0, t2=1e-2, two_nu=5):
+    rng = np.random.default_rng(seed)
+    X = rng.random((n, d))
+    th = _theta(beta, s2, t2)
+    S = O.cov_matrix(X, X, th, two_nu, True)
+    y = np.linalg.cholesky(S) @ rng.standard_normal(n)
+    return X, y, th
+
+
+# --- Matern closed forms: Sec. 4.4 Eq. (maternkernel), literal in r --------
+@pytest.mark.parametrize("two_nu", TWO_NU)
+def test_matern_closed_form_matches_bessel(two_nu):
+    nu = two_nu / 2
+    r = np.linspace(1e-3, 8.0, 300)
+    ref = 2 ** (1 - nu) / gamma(nu) * r ** nu * kv(nu, r)
+    got = np.array([O.rho(x, two_nu) for x in r])
+    assert np.max(np.abs(got - ref)) < 5e-15
+    assert O.rho(0.0, two_nu) == 1.0
+
+
+@pytest.mark.parametrize("two_nu", TWO_NU)
+def test_matern_derivative_matches_fd(two_nu):
+    # -rho'(r)/r against central differences of the Bessel-K definition
+    nu = two_nu / 2
+    f = lambda r: 2 ** (1 - nu) / gamma(nu) * r ** nu * kv(nu, r)
+    for r in (0.05, 0.3, 1.0, 2.5, 6.0):
+        h = 1e-6 * max(r, 1.0)
+        fd = -(f(r + h) - f(r - h)) / (2 * h) / r
+        assert abs(O.mdrho_over_r(r, two_nu) - fd) < 1e-7 * max(1.0, abs(fd))
+
+
+def test_nugget_on_diagonal_only():
+    rng = np.random.default_rng(1)
+    X = rng.random((5, 2))
+    X[3] = X[1]  # duplicate location, distinct observation
+    th = _theta([0.5, 0.5], 2.0, 0.25)
+    S = O.cov_matrix(X, X, th, 3, True)
+    assert np.allclose(np.diag(S), 2.25)
+    assert S[1, 3] == pytest.approx(2.0)  # sigma^2 rho(0), no nugget off the diagonal
+
+
+# --- Exact GP, Eq. (1) -------------------------------------------------------
+@pytest.mark.parametrize("two_nu", TWO_NU)
+def test_exact_loglik_matches_scipy_mvn(two_nu):
+    X, y, th = _data(150, 3, 2, [0.3, 0.6, 1.2], two_nu=two_nu)
+    S = O.cov_matrix(X, X, th, two_nu, True)
+    ref = multivariate_normal(np.zeros(len(y)), S).logpdf(y)
+    assert abs(O.exact_loglik(X, y, th, two_nu) - ref) < 1e-10 * abs(ref)
+
+
+def test_exact_gradient_matches_fd():
+    X, y, th = _data(120, 3, 3, [0.3, 0.6, 1.2])
+    _, g = O.exact_loglik(X, y, th, 5, grad=True)
+    h = 1e-5
+    for k in range(len(th)):
+        e = np.zeros_like(th)
+        e[k] = h
+        fd = (O.exact_loglik(X, y, th + e, 5) - O.exact_loglik(X, y, th - e, 5)) / (2 * h)
+        assert abs(g[k] - fd) < 1e-5 * max(1.0, abs(fd))
+
+
+# --- Block Vecchia: chain rule (Sec. 4.2) ------------------------------------
+@pytest.mark.parametrize("two_nu", TWO_NU)
+def test_full_conditioning_is_exact(two_nu):
+    """P1: when every block conditions on all earlier points the block product is
+    the exact chain-rule factorisation, so l_SBV = l_exact (values and gradients)."""
+    X, y, th = _data(240, 4, 4, [0.2, 0.5, 1.0, 2.0], two_nu=two_nu)
+    S = O.build(X, np.exp(th[:4]), K=25, m=10 ** 6, lloyd_iters=4, seed=7)
+    ll, g = O.sbv_loglik(X, y, S, th, two_nu, grad=True)
+    ex, gex = O.exact_loglik(X, y, th, two_nu, grad=True)
+    assert abs(ll - ex) < 1e-11 * abs(ex)
+    assert np.max(np.abs(g - gex)) < 1e-9 * max(1.0, np.max(np.abs(gex)))
+
+
+def test_single_block_is_exact():
+    """P2: K = 1 is one unconditioned block, i.e. Eq. (1)."""
+    X, y, th = _data(90, 3, 5, [0.3, 0.4, 0.5])
+    S = O.build(X, np.exp(th[:3]), K=1, m=50, lloyd_iters=0, seed=0)
+    assert S.K == 1 and len(S.nn_idx) == 0
+    assert abs(O.sbv_loglik(X, y, S, th, 5) - O.exact_loglik(X, y, th, 5)) < 1e-12 * 200
+
+
+def test_block_term_is_joint_minus_conditioning_logpdf():
+    """P3: each Alg. 5 block term equals log N(y_A; Sigma_A) - log N(y_J; Sigma_J)."""
+    X, y, th = _data(400, 3, 6, [0.2, 0.3, 0.9])
+    S = O.build(X, np.exp(th[:3]), K=40, m=25, lloyd_iters=5, seed=2)
+    _, lb = O.sbv_loglik(X, y, S, th, 5, blocks=True)
+    for r in range(S.K):
+        B, J = S.block(r)
+        A = np.r_[J, B]
+        SA = O.cov_matrix(X[A], X[A], th, 5, True)
+        ref = multivariate_normal(np.zeros(len(A)), SA).logpdf(y[A])
+        if len(J):
+            SJ = O.cov_matrix(X[J], X[J], th, 5, True)
+            ref -= multivariate_normal(np.zeros(len(J)), SJ).logpdf(y[J])
+        assert abs(lb[r] - ref) < 1e-11 * max(1.0, abs(ref))
+
+
+def test_nugget_only_limit():
+    """P4: with sigma^2 -> 0 every observation is independent N(0, tau^2)."""
+    X, y, _ = _data(300, 3, 7, [0.2, 0.3, 0.9])
+    th = _theta([0.2, 0.3, 0.9], np.exp(-60.0), 0.3)
+    S = O.build(X, [0.2, 0.3, 0.9], K=30, m=20, seed=1)
+    ref = -0.5 * len(y) * np.log(2 * np.pi * 0.3) - y @ y / (2 * 0.3)
+    assert abs(O.sbv_loglik(X, y, S, th, 5) - ref) < 1e-12 * abs(ref)
+
+
+def test_no_conditioning_is_independent_blocks():
+    """P5: m = 0 gives a product of independent block densities."""
+    X, y, th = _data(200, 2, 8, [0.2, 0.4])
+    S = O.build(X, np.exp(th[:2]), K=20, m=0, seed=3)
+    ref = 0.0
+    for r in range(S.K):
+        B, J = S.block(r)
+        assert len(J) == 0
+        ref += multivariate_normal(np.zeros(len(B)), O.cov_matrix(X[B], X[B], th, 5, True)).logpdf(y[B])
+    assert abs(O.sbv_loglik(X, y, S, th, 5) - ref) < 1e-12 * abs(ref)
+
+
+def test_ou_markov_exactness():
+    """P6: d = 1, nu = 1/2, no nugget (Ornstein-Uhlenbeck, Markov): contiguous
+    interval blocks ordered left to right with m >= 1 are exact, because the
+    nearest earlier point to each block centroid is its predecessor."""
+    rng = np.random.default_rng(9)
+    n = 400
+    x = np.sort(rng.random(n))[:, None]
+    th = _theta([0.3], 1.5, 1e-300)
+    S0 = O.cov_matrix(x, x, th, 1, True)
+    y = np.linalg.cholesky(S0) @ rng.standard_normal(n)
+    bs = 8
+    bp = np.arange(0, n + 1, bs)
+    pts = np.arange(n)
+    K = len(bp) - 1
+    nn_ptr = np.r_[0, 0, np.arange(1, K)]
+    nn_idx = bp[1:-1] - 1  # predecessor point of every block after the first
+    S = O.Structure(n, 1, 1, bp, pts, nn_ptr, nn_idx)
+    ex = O.exact_loglik(x, y, th, 1)
+    assert abs(O.sbv_loglik(x, y, S, th, 1) - ex) < 1e-11 * abs(ex)
+
+
+def test_kl_nonnegative_and_nonincreasing_in_m():
+    """P7 / Eq. (kldivergence): KL = l_exact(0) - l_SBV(0) >= 0, and larger
+    nested conditioning sets cannot increase it."""
+    X, _, th = _data(300, 4, 10, [0.1, 0.3, 1.0, 3.0])
+    y0 = np.zeros(300)
+    ex0 = O.exact_loglik(X, y0, th, 7)
+    kls = []
+    for m in (0, 5, 10, 20, 40, 80, 300):
+        S = O.build(X, np.exp(th[:4]), K=30, m=m, lloyd_iters=5, seed=11)
+        kls.append(ex0 - O.sbv_loglik(X, y0, S, th, 7))
+    assert all(k >= -1e-9 for k in kls)
+    assert all(a >= b - 1e-9 for a, b in zip(kls, kls[1:]))
+    assert abs(kls[-1]) < 1e-9
+
+
+def test_quadratic_form_expectation_tiny():
+    """P8: with y drawn from the exact GP, E[sum_i u_i] = tr(S_vecchia^{-1} S) and for
+    m >= n this is exactly n; checked through E over y of -2(l(y) - l(0))."""
+    X, _, th = _data(60, 2, 12, [0.3, 0.5])
+    S = O.build(X, np.exp(th[:2]), K=6, m=60, seed=1)
+    Sig = O.cov_matrix(X, X, th, 5, True)
+    # -2(l(y)-l(0)) = y^T Q y with Q the Vecchia precision; E = tr(Q Sig) = n.
+    # Recover Q columnwise from the oracle (polarisation), then the trace.
+    n = 60
+    l0 = O.sbv_loglik(X, np.zeros(n), S, th, 5)
+    q = lambda v: -2.0 * (O.sbv_loglik(X, v, S, th, 5) - l0)
+    E = np.eye(n)
+    diag = np.array([q(E[i]) for i in range(n)])
+    tr = 0.0
+    for i in range(n):
+        for j in range(n):
+            qij = diag[i] if i == j else 0.5 * (q(E[i] + E[j]) - diag[i] - diag[j])
+            tr += qij * Sig[j, i]
+    assert abs(tr - n) < 1e-8 * n
+
+
+def test_invariances():
+    """P9: scaling x and beta jointly, translating x, permuting dimensions with
+    beta, and permuting points inside blocks and conditioning sets."""
+    X, y, th = _data(200, 3, 13, [0.2, 0.5, 1.1])
+    S = O.build(X, np.exp(th[:3]), K=20, m=15, seed=4)
+    base = O.sbv_loglik(X, y, S, th, 5)
+    th2 = th.copy()
+    th2[:3] += np.log(3.0)
+    assert abs(O.sbv_loglik(3.0 * X, y, S, th2, 5) - base) < 1e-12 * abs(base)
+    assert abs(O.sbv_loglik(X + 7.25, y, S, th, 5) - base) < 1e-11 * abs(base)
+    p = [2, 0, 1]
+    th3 = np.r_[th[:3][p], th[3:]]
+    assert abs(O.sbv_loglik(X[:, p], y, S, th3, 5) - base) < 1e-12 * abs(base)
+    rng = np.random.default_rng(0)
+    pts, nidx = S.block_pts.copy(), S.nn_idx.copy()
+    for r in range(S.K):
+        a, b = S.block_ptr[r], S.block_ptr[r + 1]
+        pts[a:b] = rng.permutation(pts[a:b])
+        a, b = S.nn_ptr[r], S.nn_ptr[r + 1]
+        nidx[a:b] = rng.permutation(nidx[a:b])
+    S2 = O.Structure(S.n, S.d, S.m, S.block_ptr, pts, S.nn_ptr, nidx)
+    assert abs(O.sbv_loglik(X, y, S2, th, 5) - base) < 1e-12 * abs(base)
+
+
+def test_sigma2_gradient_identity_without_nugget():
+    """P10: with tau^2 = 0 the model is sigma^2 times a fixed correlation, so
+    dl/dlog sigma^2 = (sum_i u_i - n)/2 with sum_i u_i = 2(l(0) - l(y))."""
+    X, y, _ = _data(180, 3, 14, [0.3, 0.6, 1.0])
+    th = _theta([0.3, 0.6, 1.0], 1.7, 1e-300)
+    S = O.build(X, [0.3, 0.6, 1.0], K=18, m=12, seed=5)
+    ll, g = O.sbv_loglik(X, y, S, th, 5, grad=True)
+    u = 2.0 * (O.sbv_loglik(X, np.zeros_like(y), S, th, 5) - ll)
+    assert abs(g[3] - (u - len(y)) / 2) < 1e-9 * max(1.0, abs(g[3]))
+
+
+@pytest.mark.parametrize("two_nu", TWO_NU)
+def test_sbv_gradient_matches_fd(two_nu):
+    """P12: block-inverse gradient against central differences (h = 1e-5)."""
+    X, y, th = _data(220, 3, 15, [0.2, 0.5, 1.1], two_nu=two_nu)
+    S = O.build(X, np.exp(th[:3]), K=22, m=14, seed=6)
+    ll, g = O.sbv_loglik(X, y, S, th, two_nu, grad=True)
+    h = 1e-5
+    for k in range(len(th)):
+        e = np.zeros_like(th)
+        e[k] = h
+        fd = (O.sbv_loglik(X, y, S, th + e, two_nu) - O.sbv_loglik(X, y, S, th - e, two_nu)) / (2 * h)
+        assert abs(g[k] - fd) < 1e-5 * max(1.0, abs(g[k])) + 10 * 2.2e-16 * abs(ll) / h
+
+
+def test_neighbours_are_exact_brute_force():
+    """P13: J_i are the m nearest points of strictly earlier blocks to the block
+    centroid in beta_build-scaled space (brute force with numpy)."""
+    rng = np.random.default_rng(16)
+    X = rng.random((500, 3))
+    bb = np.array([0.1, 0.4, 2.0])
+    S = O.build(X, bb, K=50, m=30, lloyd_iters=3, seed=8)
+    Z = X / bb
+    rank_of = np.empty(500, np.int64)
+    for r in range(S.K):
+        rank_of[S.block_pts[S.block_ptr[r]:S.block_ptr[r + 1]]] = r
+    for r in range(S.K):
+        B, J = S.block(r)
+        c = Z[B].mean(0)
+        earlier = S.block_pts[:S.block_ptr[r]]
+        assert len(J) == min(30, len(earlier))
+        if len(J) == 0:
+            continue
+        assert np.all(rank_of[J] < r)
+        d2 = ((Z[earlier] - c) ** 2).sum(1)
+        kth = np.sort(d2)[len(J) - 1]
+        dj = ((Z[J] - c) ** 2).sum(1)
+        assert np.all(dj <= kth * (1 + 1e-12))
+        assert np.all(np.diff(dj) >= -1e-15)
+
+
+def test_kmeans_objective_and_bounds():
+    """P14: Lloyd passes never increase the k-means objective; RAC is zero passes;
+    size bounds hold; blocks partition the points."""
+    rng = np.random.default_rng(17)
+    X = rng.random((3000, 4))
+    S = O.build(X, np.ones(4), K=150, m=10, lloyd_iters=8, min_bs=5, max_bs=60, seed=9)
+    obj = S.kmeans_obj
+    assert len(obj) >= 2 and np.all(np.diff(obj) <= 1e-9 * obj[0])
+    sizes = np.diff(S.block_ptr)
+    assert sizes.min() >= 5 and sizes.max() <= 60
+    assert np.array_equal(np.sort(S.block_pts), np.arange(3000))
+    R = O.build(X, np.ones(4), K=150, m=10, lloyd_iters=0, seed=9)
+    assert len(R.kmeans_obj) == 1
+
+
+def test_sampler_with_full_conditioning_is_cholesky_draw():
+    """O6: visiting blocks in rank order and drawing y_B = mu + L' xi_B with every
+    earlier point conditioned on reproduces y = chol(Sigma) xi in that order."""
+    rng = np.random.default_rng(18)
+    n = 150
+    X = rng.random((n, 3))
+    th = _theta([0.3, 0.5, 0.8], 1.2, 1e-3)
+    S = O.build(X, [0.3, 0.5, 0.8], K=15, m=n, seed=3)
+    xi = rng.standard_normal(n)
+    y = O.sample(X, S, th, 5, xi)
+    P = S.block_pts
+    L = np.linalg.cholesky(O.cov_matrix(X[P], X[P], th, 5, True))
+    assert np.max(np.abs(y[P] - L @ xi[P])) < 1e-10
