@@ -1,0 +1,154 @@
+/*
+ * sbv.h -- C ABI of the MI355X Scaled Block Vecchia (SBV) log-likelihood library
+ * (libsbv.so).  Plain pointers and sizes only.
+ *
+ * The method: the inputs X (n x d) are scaled by anisotropic ranges (Alg. 2),
+ * clustered into blocks (k-means, or random anchors, Alg. 3), the blocks are put
+ * in a uniformly random order (Alg. 1), and every block conditions on the m points
+ * of strictly earlier blocks nearest its centroid (Alg. 4, Sec. 4.2 Eq.
+ * (mmsearchingBV)).  The log-likelihood is the sum over blocks of the
+ * conditional Gaussian log-densities of Alg. 5 with the Matern kernel of
+ * Sec. 4.4 Eq. (scale)/(maternkernel).
+ *
+ * Conventions shared by every entry point:
+ *  - theta of one dataset packs d+2 log-parameters
+ *      [log beta_1 .. log beta_d, log sigma^2, log tau^2]
+ *    (ranges, process variance, nugget).  The nugget is added on the diagonal
+ *    only.  The Matern smoothness is fixed per dataset and passed as two_nu in
+ *    {1, 3, 5, 7} (nu = 1/2, 3/2, 5/2, 7/2, closed forms of Eq. (maternkernel)
+ *    taken literally in r, i.e. without a sqrt(2 nu) factor).
+ *  - Each block term carries -(b_i/2) log(2 pi), so conditioning every block on
+ *    all earlier points reproduces the exact log-likelihood of Eq. (1).
+ *  - Ownership: the caller owns every buffer it passes; the library copies what
+ *    it keeps (a handle owns its device copies).  Host entry points are
+ *    synchronous.  *_dev entry points take device pointers and a HIP stream
+ *    (passed as void*) and are asynchronous: their buffers must stay valid until
+ *    the stream reaches that point.
+ *  - Errors: every function returns an sbv_status; on failure outputs are left
+ *    untouched unless stated, and sbv_last_error() describes the failure.
+ *  - One handle must not be used from two host threads at once.
+ */
+#ifndef SBV_H
+#define SBV_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SBV_OK = 0,
+  SBV_E_INVAL = 1,  /* bad argument (NaN/inf, sizes, unsupported nu, bad structure) */
+  SBV_E_NOMEM = 2,  /* host or device allocation failed                             */
+  SBV_E_DEVICE = 3, /* HIP error or no device                                       */
+  SBV_E_NOTPD = 4,  /* a block is not positive definite even in FP64                */
+  SBV_E_NOCONV = 5  /* sbv_fit reached its evaluation limit                          */
+} sbv_status;
+
+enum { SBV_FP64 = 0, SBV_FP32 = 1 };
+enum { SBV_KMEANS = 0, SBV_RAC = 1 };
+enum { SBV_NELDER_MEAD = 0, SBV_LBFGS = 1 };
+
+/* Opaque handle: one dataset with its block structure, resident on the device. */
+typedef struct sbv_blocks_s* sbv_blocks;
+
+typedef struct {
+  int32_t method;      /* SBV_KMEANS or SBV_RAC (Alg. 3: random anchors, no Lloyd pass) */
+  int32_t lloyd_iters; /* k-means passes after the anchor assignment (ignored for RAC)   */
+  int32_t min_bs;      /* smallest block size (0: no bound)                              */
+  int32_t max_bs;      /* largest block size (0: no bound)                               */
+  int32_t reserved;    /* must be 0                                                      */
+  uint64_t seed;       /* anchors use seed, the block order seed + 1                     */
+} sbv_build_opts;
+
+/*
+ * Build the block structure on the device (Alg. 2 scaling by beta_build, Alg. 3
+ * anchors + optional k-means, random block order of Alg. 1, block centroids and
+ * the exact m nearest points of strictly earlier blocks of Alg. 4 -- brute force,
+ * no distance threshold).  X: host, row-major n x d FP64; y: host, n FP64 (may be
+ * NULL: observations set to 0).  n_blocks: requested block count K (<= n); the
+ * final count can differ when size bounds split or merge clusters.  m >= 0.
+ * On success *out owns device copies of X and y in block order.
+ */
+sbv_status sbv_build_blocks(const double* X, const double* y, int64_t n, int32_t d,
+                            const double* beta_build, int64_t n_blocks, int32_t m,
+                            const sbv_build_opts* opts, sbv_blocks* out);
+
+/*
+ * Create a handle from an explicit structure (exchange format).  block_ptr
+ * (K+1) and block_pts (n) list the blocks in rank order as original point ids;
+ * nn_ptr (K+1) and nn_idx (nn_ptr[K]) list each block's conditioning points as
+ * original ids.  Every neighbour must belong to a strictly earlier block and
+ * every point to exactly one block; otherwise SBV_E_INVAL.  Conditioning and
+ * block sizes are limited to m_i + b_i <= sbv_max_joint_size().
+ */
+sbv_status sbv_blocks_import(const double* X, const double* y, int64_t n, int32_t d, int64_t K,
+                             const int64_t* block_ptr, const int64_t* block_pts,
+                             const int64_t* nn_ptr, const int64_t* nn_idx, sbv_blocks* out);
+
+/* Sizes of a handle: points, dimension, blocks, total conditioning entries. */
+sbv_status sbv_blocks_info(sbv_blocks h, int64_t* n, int32_t* d, int64_t* K, int64_t* nnz_nn);
+
+/* Read the structure back in the exchange format (host arrays sized by info). */
+sbv_status sbv_blocks_export(sbv_blocks h, int64_t* block_ptr, int64_t* block_pts,
+                             int64_t* nn_ptr, int64_t* nn_idx);
+
+/* Replace the observations (host, n FP64 in original point order). */
+sbv_status sbv_blocks_set_y(sbv_blocks h, const double* y);
+
+/* Replace the observations from a device buffer (n FP64, original order). */
+sbv_status sbv_blocks_set_y_dev(sbv_blocks h, const double* y_dev, void* stream);
+
+/* Free a handle; NULL-safe. */
+void sbv_blocks_free(sbv_blocks h);
+
+/* Largest joint size m_i + b_i a block may have. */
+int32_t sbv_max_joint_size(void);
+
+/*
+ * SBV log-likelihood of n_sets datasets (Alg. 5 summed over blocks, Alg. 1
+ * Step 5 as an on-device FP64 reduction).  theta: host, packed per set
+ * (d_j + 2 values each, sets in order); two_nu: host, one per set; prec:
+ * SBV_FP64, or SBV_FP32 (FP32 covariance and Cholesky, FP64 log-det and
+ * quadratic-form accumulation; blocks with a pivot below threshold are
+ * recomputed in FP64).  loglik: host, n_sets values.  If a block is not
+ * positive definite in FP64, that set's value is -inf and SBV_E_NOTPD is
+ * returned (other sets stay valid).
+ */
+sbv_status sbv_loglik(const sbv_blocks* sets, int32_t n_sets, const double* theta,
+                      const int32_t* two_nu, int32_t prec, double* loglik);
+
+/* Device variant: theta_dev and loglik_dev are device pointers; the work is
+ * queued on `stream` (a hipStream_t; NULL = default stream) with no host
+ * synchronisation.  Non-positive-definite sets give -inf. */
+sbv_status sbv_loglik_dev(const sbv_blocks* sets, int32_t n_sets, const double* theta_dev,
+                          const int32_t* two_nu, int32_t prec, double* loglik_dev, void* stream);
+
+/*
+ * Log-likelihood and its gradient with respect to the packed log-parameters
+ * (structure and nu held fixed), from a hand-written adjoint of the block
+ * factorisation.  grad: n_sets packed (d_j + 2) values, same order as theta.
+ */
+sbv_status sbv_loglik_grad(const sbv_blocks* sets, int32_t n_sets, const double* theta,
+                           const int32_t* two_nu, int32_t prec, double* loglik, double* grad);
+sbv_status sbv_loglik_grad_dev(const sbv_blocks* sets, int32_t n_sets, const double* theta_dev,
+                               const int32_t* two_nu, int32_t prec, double* loglik_dev,
+                               double* grad_dev, void* stream);
+
+/* Number of blocks recomputed in FP64 by the last SBV_FP32 evaluation of this
+ * handle (synchronises the device). */
+sbv_status sbv_blocks_fallback_count(sbv_blocks h, int64_t* count);
+
+/* Per-block terms l_i of the last evaluation of this handle, in rank order
+ * (host, K values; synchronises the device). */
+sbv_status sbv_blocks_terms(sbv_blocks h, double* terms);
+
+/* Message of the last failure on the calling thread (valid until the next call). */
+const char* sbv_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SBV_H */

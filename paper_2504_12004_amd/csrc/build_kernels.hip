@@ -1,0 +1,184 @@
+// Device kernels of the block builder (Alg. 3 assignment, Alg. 4 neighbour
+// search), FP64 throughout so that distances match a plain CPU evaluation of
+// sum_k (z_k - c_k)^2 in dimension order.
+#include <hip/hip_runtime.h>
+
+#include "sbv_internal.h"
+
+namespace sbv {
+
+// ---- nearest centre (Alg. 3 line "assign to the nearest anchor") -----------
+// One thread per point; centres streamed through LDS in tiles.  Ties go to the
+// lower centre id (strict comparison while scanning ids upward).
+constexpr int kAssignTile = 256;
+
+__global__ __launch_bounds__(256) void k_assign(const double* __restrict__ Z, int64_t n, int d,
+                                                const double* __restrict__ C, int K,
+                                                int32_t* __restrict__ lab, double* __restrict__ best_d2) {
+  __shared__ double cs[kAssignTile * kMaxDim];
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double z[kMaxDim];
+#pragma unroll
+  for (int k = 0; k < kMaxDim; ++k) z[k] = (i < n && k < d) ? Z[i * d + k] : 0.0;
+  double best = __builtin_inf();
+  int bj = 0;
+  for (int c0 = 0; c0 < K; c0 += kAssignTile) {
+    const int cn = min(kAssignTile, K - c0);
+    __syncthreads();
+    for (int e = threadIdx.x; e < cn * d; e += blockDim.x) cs[e] = C[(int64_t)c0 * d + e];
+    __syncthreads();
+    for (int c = 0; c < cn; ++c) {
+      double s = 0.0;
+#pragma unroll
+      for (int k = 0; k < kMaxDim; ++k) {
+        if (k < d) {
+          double t = z[k] - cs[c * d + k];
+          s += t * t;
+        }
+      }
+      if (s < best) {
+        best = s;
+        bj = c0 + c;
+      }
+    }
+  }
+  if (i < n) {
+    lab[i] = bj;
+    if (best_d2) best_d2[i] = best;
+  }
+}
+
+hipError_t launch_assign(const double* Z, int64_t n, int d, const double* C, int K, int32_t* lab,
+                         double* best_d2, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_assign, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, Z, n, d, C, K, lab, best_d2);
+  return hipGetLastError();
+}
+
+// ---- exact m nearest earlier points of each block centre (Alg. 4) ---------
+// One wave per query block, eight queries per workgroup sharing point tiles in
+// LDS.  Each wave keeps a candidate buffer of (distance, position) pairs below
+// its running threshold tau (the m-th smallest distance kept so far); when the
+// buffer could overflow it is sorted and cut back to m entries.  Ties order by
+// ordered position, so the result is the exact brute-force answer.
+constexpr int kKnnWaves = 8;
+constexpr int kKnnTile = 256;
+constexpr int kKnnCap = 1024;
+
+struct KnnSmem {
+  double pts[kKnnTile * kMaxDim];
+  double bd[kKnnWaves][kKnnCap];
+  int32_t bp[kKnnWaves][kKnnCap];
+};
+
+__device__ __forceinline__ bool knn_less(double da, int pa, double db, int pb) {
+  return da < db || (da == db && pa < pb);
+}
+
+// Sort the first `cnt` entries of one wave's buffer (padding to the next power
+// of two with +inf), bitonic network executed by the 64 lanes of the wave.
+__device__ void knn_sort(double* bd, int32_t* bp, int cnt, int lane) {
+  int len = 64;
+  while (len < cnt) len <<= 1;
+  for (int e = cnt + lane; e < len; e += 64) {
+    bd[e] = __builtin_inf();
+    bp[e] = 0x7fffffff;
+  }
+  __builtin_amdgcn_s_waitcnt(0);
+  __builtin_amdgcn_wave_barrier();
+  for (int k = 2; k <= len; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int e = lane; e < len; e += 64) {
+        int p = e ^ j;
+        if (p > e) {
+          double de = bd[e], dp = bd[p];
+          int pe = bp[e], pp = bp[p];
+          bool up = (e & k) == 0;
+          bool sw = up ? knn_less(dp, pp, de, pe) : knn_less(de, pe, dp, pp);
+          if (sw) {
+            bd[e] = dp;
+            bd[p] = de;
+            bp[e] = pp;
+            bp[p] = pe;
+          }
+        }
+      }
+      __builtin_amdgcn_s_waitcnt(0);
+      __builtin_amdgcn_wave_barrier();
+    }
+  }
+}
+
+__global__ __launch_bounds__(kKnnWaves * 64) void k_knn(const double* __restrict__ Z, int d,
+                                                        const double* __restrict__ cen,
+                                                        const int32_t* __restrict__ bptr, int K, int m,
+                                                        const int64_t* __restrict__ nn_ptr,
+                                                        int32_t* __restrict__ nn_pos) {
+  __shared__ KnnSmem sm;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int q0 = blockIdx.x * kKnnWaves;
+  const int q = q0 + wave;
+  const bool active = q < K;
+  const int prefix = active ? bptr[q] : 0;  // points of strictly earlier blocks
+  const int qlast = min(q0 + kKnnWaves, K) - 1;
+  const int maxprefix = bptr[qlast];
+  double c[kMaxDim];
+#pragma unroll
+  for (int k = 0; k < kMaxDim; ++k) c[k] = (active && k < d) ? cen[(int64_t)q * d + k] : 0.0;
+  double* bd = sm.bd[wave];
+  int32_t* bpos = sm.bp[wave];
+  int cnt = 0;
+  double tau = __builtin_inf();
+  for (int p0 = 0; p0 < maxprefix; p0 += kKnnTile) {
+    const int pn = min(kKnnTile, maxprefix - p0);
+    __syncthreads();
+    for (int e = tid; e < pn * d; e += kKnnWaves * 64) sm.pts[e] = Z[(int64_t)p0 * d + e];
+    __syncthreads();
+    if (!active || p0 >= prefix) continue;
+    if (cnt > kKnnCap - kKnnTile) {
+      knn_sort(bd, bpos, cnt, lane);
+      cnt = min(cnt, m);
+      tau = (cnt >= m) ? bd[m - 1] : __builtin_inf();
+    }
+    const int lim = min(pn, prefix - p0);
+    for (int t0 = 0; t0 < kKnnTile; t0 += 64) {
+      const int t = t0 + lane;
+      double s = __builtin_inf();
+      if (t < lim) {
+        s = 0.0;
+#pragma unroll
+        for (int k = 0; k < kMaxDim; ++k) {
+          if (k < d) {
+            double df = sm.pts[t * d + k] - c[k];
+            s += df * df;
+          }
+        }
+      }
+      const bool keep = t < lim && s <= tau;
+      const unsigned long long mask = __ballot(keep);
+      if (keep) {
+        const int off = __popcll(mask & ((1ull << lane) - 1ull));
+        bd[cnt + off] = s;
+        bpos[cnt + off] = p0 + t;
+      }
+      cnt += __popcll(mask);
+    }
+  }
+  if (!active) return;
+  const int mi = (int)(nn_ptr[q + 1] - nn_ptr[q]);
+  if (mi == 0) return;
+  knn_sort(bd, bpos, cnt, lane);
+  for (int e = lane; e < mi; e += 64) nn_pos[nn_ptr[q] + e] = bpos[e];
+}
+
+hipError_t launch_knn(const double* Z, int d, const double* cen, const int32_t* bptr, int K, int m,
+                      const int64_t* nn_ptr, int32_t* nn_pos, hipStream_t s) {
+  if (K <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_knn, dim3((K + kKnnWaves - 1) / kKnnWaves), dim3(kKnnWaves * 64), 0, s, Z, d, cen,
+                     bptr, K, m, nn_ptr, nn_pos);
+  return hipGetLastError();
+}
+
+int knn_max_m() { return kKnnCap - kKnnTile; }
+
+}  // namespace sbv

@@ -1,0 +1,63 @@
+// Internal types shared by the HIP kernels and the C-ABI layer of libsbv.so.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+namespace sbv {
+
+// Tile edge of every block factorisation (the 16x16 MFMA output tile).
+constexpr int kTile = 16;
+// Largest input dimension supported by the fused kernels.
+constexpr int kMaxDim = 20;
+
+// One dataset as the kernels see it: points in block-rank order.
+struct SetDesc {
+  const double* X;        // n x d, row-major, rank order
+  const double* y;        // n, rank order
+  const int32_t* bptr;    // K+1 block offsets into the ordered points
+  const int64_t* nptr;    // K+1 offsets into nidx
+  const int32_t* nidx;    // conditioning points as ordered positions
+  double* llb;            // K per-block terms (output)
+  int32_t* flag;          // K per-block status (output): bit0 fp32 pivot flag, bit1 not PD
+  double* gradb;          // K x (d+2) per-block gradient terms (output, gradient kernels)
+  int32_t d;
+  int32_t two_nu;
+  int32_t theta_off;      // offset of this set's d+2 parameters in the theta buffer
+  int32_t K;
+};
+
+// One unit of work: block `block` of set `set`.
+struct WorkItem {
+  int32_t set;
+  int32_t block;
+};
+
+// Kernel variant: register-tile capacity NTM tiles per side, NW waves.
+struct Variant {
+  int ntm;
+  int nw;
+};
+
+// Launchers (kernels.hip).  `count` is a device int; the kernel loops over
+// items[blockIdx.x + k*gridDim.x] while the index is below *count.
+hipError_t launch_loglik(int prec, int variant, int grid, const SetDesc* sets, const double* theta,
+                         const WorkItem* items, const int* count, double piv_tau, hipStream_t s);
+int n_variants();
+Variant variant(int v);
+int variant_for(int nA);  // smallest variant holding a joint size nA, or -1
+hipError_t launch_reduce(const SetDesc* sets, int n_sets, const int* set_k, double* out, int* bad,
+                         hipStream_t s);
+hipError_t launch_flag_compact(const SetDesc* sets, const WorkItem* items, const int* count,
+                               WorkItem* out_items, int* out_count, hipStream_t s);
+hipError_t launch_zero_int(int* p, int n, hipStream_t s);
+int max_grid(int prec, int variant);
+
+}  // namespace sbv
+
+namespace sbv {
+hipError_t launch_scatter_y(const double* y, const int32_t* pos_of, double* y_ord, int64_t n,
+                            hipStream_t s);
+}  // namespace sbv

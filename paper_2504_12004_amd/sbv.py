@@ -1,0 +1,246 @@
+"""Thin ctypes binding of libsbv.so (argument marshalling only).
+
+Every function here carries the name of the C entry point it calls
+(include/sbv.h) and only converts arguments; all computation happens in the
+HIP library.  If libsbv.so is missing the first call raises -- there is no
+fallback path.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libsbv.so")
+_LIB = None
+
+SBV_OK, SBV_E_INVAL, SBV_E_NOMEM, SBV_E_DEVICE, SBV_E_NOTPD, SBV_E_NOCONV = range(6)
+SBV_FP64, SBV_FP32 = 0, 1
+SBV_KMEANS, SBV_RAC = 0, 1
+SBV_NELDER_MEAD, SBV_LBFGS = 0, 1
+
+_d = C.POINTER(C.c_double)
+_i64 = C.POINTER(C.c_int64)
+_i32 = C.POINTER(C.c_int32)
+_h = C.c_void_p
+
+
+class SBVError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"sbv status {status}: {msg}")
+        self.status = status
+
+
+class sbv_build_opts(C.Structure):
+    _fields_ = [("method", C.c_int32), ("lloyd_iters", C.c_int32), ("min_bs", C.c_int32),
+                ("max_bs", C.c_int32), ("reserved", C.c_int32), ("seed", C.c_uint64)]
+
+
+class sbv_fit_opts(C.Structure):
+    _fields_ = [("optimizer", C.c_int32), ("prec", C.c_int32), ("fp64_polish", C.c_int32),
+                ("max_evals", C.c_int32), ("ftol", C.c_double), ("gtol", C.c_double),
+                ("rebuild_rounds", C.c_int32), ("lbfgs_m", C.c_int32), ("init_step", C.c_double),
+                ("checkpoint_path", C.c_char_p)]
+
+
+def lib():
+    """Load libsbv.so (raises if it has not been built)."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(_LIB_PATH):
+        raise RuntimeError(f"{_LIB_PATH} is missing: build it with paper_2504_12004_amd/build.py")
+    L = C.CDLL(_LIB_PATH)
+    sig = {
+        "sbv_last_error": (C.c_char_p, []),
+        "sbv_max_joint_size": (C.c_int32, []),
+        "sbv_build_blocks": (C.c_int, [_d, _d, C.c_int64, C.c_int32, _d, C.c_int64, C.c_int32,
+                                       C.POINTER(sbv_build_opts), C.POINTER(_h)]),
+        "sbv_blocks_import": (C.c_int, [_d, _d, C.c_int64, C.c_int32, C.c_int64, _i64, _i64, _i64, _i64,
+                                        C.POINTER(_h)]),
+        "sbv_blocks_info": (C.c_int, [_h, _i64, _i32, _i64, _i64]),
+        "sbv_blocks_export": (C.c_int, [_h, _i64, _i64, _i64, _i64]),
+        "sbv_blocks_set_y": (C.c_int, [_h, _d]),
+        "sbv_blocks_set_y_dev": (C.c_int, [_h, C.c_void_p, C.c_void_p]),
+        "sbv_blocks_free": (None, [_h]),
+        "sbv_loglik": (C.c_int, [C.POINTER(_h), C.c_int32, _d, _i32, C.c_int32, _d]),
+        "sbv_loglik_dev": (C.c_int, [C.POINTER(_h), C.c_int32, C.c_void_p, _i32, C.c_int32, C.c_void_p,
+                                     C.c_void_p]),
+        "sbv_loglik_grad": (C.c_int, [C.POINTER(_h), C.c_int32, _d, _i32, C.c_int32, _d, _d]),
+        "sbv_loglik_grad_dev": (C.c_int, [C.POINTER(_h), C.c_int32, C.c_void_p, _i32, C.c_int32, C.c_void_p,
+                                          C.c_void_p, C.c_void_p]),
+        "sbv_blocks_fallback_count": (C.c_int, [_h, _i64]),
+        "sbv_blocks_terms": (C.c_int, [_h, _d]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _LIB = L
+    return L
+
+
+def _check(st):
+    if st != SBV_OK:
+        raise SBVError(st, lib().sbv_last_error().decode())
+
+
+def _c64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _ci64(a):
+    return np.ascontiguousarray(a, dtype=np.int64)
+
+
+def _p(a, t=_d):
+    return a.ctypes.data_as(t)
+
+
+class Blocks:
+    """Owning wrapper of an sbv_blocks handle."""
+
+    def __init__(self, handle):
+        self.handle = C.c_void_p(handle)
+        n, d, K, nnz = C.c_int64(), C.c_int32(), C.c_int64(), C.c_int64()
+        _check(lib().sbv_blocks_info(self.handle, C.byref(n), C.byref(d), C.byref(K), C.byref(nnz)))
+        self.n, self.d, self.K, self.nnz = n.value, d.value, K.value, nnz.value
+
+    def free(self):
+        if self.handle is not None and self.handle.value:
+            lib().sbv_blocks_free(self.handle)
+        self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def sbv_blocks_import(X, y, block_ptr, block_pts, nn_ptr, nn_idx):
+    X = _c64(X)
+    n, d = X.shape
+    y = None if y is None else _c64(y)
+    bp, pts, npt, nid = _ci64(block_ptr), _ci64(block_pts), _ci64(nn_ptr), _ci64(nn_idx)
+    if len(nid) == 0:
+        nid = np.zeros(1, np.int64)
+    h = C.c_void_p()
+    _check(lib().sbv_blocks_import(_p(X), _p(y) if y is not None else None, n, d, len(bp) - 1, _p(bp, _i64),
+                                   _p(pts, _i64), _p(npt, _i64), _p(nid, _i64), C.byref(h)))
+    return Blocks(h.value)
+
+
+def sbv_build_blocks(X, y, beta_build, n_blocks, m, method=SBV_KMEANS, lloyd_iters=10, min_bs=0, max_bs=0,
+                     seed=0):
+    X = _c64(X)
+    n, d = X.shape
+    y = None if y is None else _c64(y)
+    bb = _c64(beta_build)
+    o = sbv_build_opts(int(method), int(lloyd_iters), int(min_bs), int(max_bs), 0, int(seed))
+    h = C.c_void_p()
+    _check(lib().sbv_build_blocks(_p(X), _p(y) if y is not None else None, n, d, _p(bb), int(n_blocks), int(m),
+                                  C.byref(o), C.byref(h)))
+    return Blocks(h.value)
+
+
+def sbv_blocks_export(b):
+    bp = np.empty(b.K + 1, np.int64)
+    pts = np.empty(b.n, np.int64)
+    npt = np.empty(b.K + 1, np.int64)
+    nid = np.empty(max(b.nnz, 1), np.int64)
+    _check(lib().sbv_blocks_export(b.handle, _p(bp, _i64), _p(pts, _i64), _p(npt, _i64), _p(nid, _i64)))
+    return bp, pts, npt, nid[:b.nnz]
+
+
+def sbv_blocks_set_y(b, y):
+    y = _c64(y)
+    _check(lib().sbv_blocks_set_y(b.handle, _p(y)))
+
+
+def sbv_blocks_set_y_dev(b, y_dev, stream=None):
+    """y_dev: a device tensor/pointer (torch tensor accepted), original order."""
+    _check(lib().sbv_blocks_set_y_dev(b.handle, C.c_void_p(_ptr(y_dev)), C.c_void_p(_stream(stream))))
+
+
+def _handles(sets):
+    if isinstance(sets, Blocks):
+        sets = [sets]
+    arr = (C.c_void_p * len(sets))(*[s.handle.value for s in sets])
+    return arr, len(sets)
+
+
+def _ptr(t):
+    if hasattr(t, "data_ptr"):
+        return t.data_ptr()
+    return int(t)
+
+
+def _stream(s):
+    if s is None:
+        return 0
+    if hasattr(s, "cuda_stream"):
+        return s.cuda_stream
+    return int(s)
+
+
+def sbv_loglik(sets, theta, two_nu, prec=SBV_FP64):
+    hs, ns = _handles(sets)
+    th = _c64(np.concatenate([np.ravel(t) for t in theta]) if isinstance(theta, (list, tuple)) else theta)
+    tn = np.ascontiguousarray(np.broadcast_to(np.asarray(two_nu, np.int32), (ns,)), dtype=np.int32)
+    out = np.empty(ns)
+    _check(lib().sbv_loglik(hs, ns, _p(th), _p(tn, _i32), int(prec), _p(out)))
+    return out
+
+
+def sbv_loglik_dev(sets, theta_dev, two_nu, out_dev, prec=SBV_FP64, stream=None):
+    hs, ns = _handles(sets)
+    tn = np.ascontiguousarray(np.broadcast_to(np.asarray(two_nu, np.int32), (ns,)), dtype=np.int32)
+    _check(lib().sbv_loglik_dev(hs, ns, C.c_void_p(_ptr(theta_dev)), _p(tn, _i32), int(prec),
+                                C.c_void_p(_ptr(out_dev)), C.c_void_p(_stream(stream))))
+
+
+def sbv_loglik_grad(sets, theta, two_nu, prec=SBV_FP64):
+    hs, ns = _handles(sets)
+    th = _c64(np.concatenate([np.ravel(t) for t in theta]) if isinstance(theta, (list, tuple)) else theta)
+    tn = np.ascontiguousarray(np.broadcast_to(np.asarray(two_nu, np.int32), (ns,)), dtype=np.int32)
+    out = np.empty(ns)
+    g = np.empty(len(th))
+    _check(lib().sbv_loglik_grad(hs, ns, _p(th), _p(tn, _i32), int(prec), _p(out), _p(g)))
+    return out, g
+
+
+def sbv_loglik_grad_dev(sets, theta_dev, two_nu, out_dev, grad_dev, prec=SBV_FP64, stream=None):
+    hs, ns = _handles(sets)
+    tn = np.ascontiguousarray(np.broadcast_to(np.asarray(two_nu, np.int32), (ns,)), dtype=np.int32)
+    _check(lib().sbv_loglik_grad_dev(hs, ns, C.c_void_p(_ptr(theta_dev)), _p(tn, _i32), int(prec),
+                                     C.c_void_p(_ptr(out_dev)), C.c_void_p(_ptr(grad_dev)),
+                                     C.c_void_p(_stream(stream))))
+
+
+def sbv_blocks_fallback_count(b):
+    c = C.c_int64()
+    _check(lib().sbv_blocks_fallback_count(b.handle, C.byref(c)))
+    return c.value
+
+
+def sbv_blocks_terms(b):
+    out = np.empty(b.K)
+    _check(lib().sbv_blocks_terms(b.handle, _p(out)))
+    return out
+
+
+def sbv_max_joint_size():
+    return lib().sbv_max_joint_size()
+
+
+def sbv_blocks_free(b):
+    b.free()
+
+
+def sbv_blocks_info(b):
+    return b.n, b.d, b.K, b.nnz
+
+
+def sbv_last_error():
+    return lib().sbv_last_error().decode()

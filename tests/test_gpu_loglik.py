@@ -1,0 +1,79 @@
+"""GPU parity of the fused SBV log-likelihood against the FP64 oracle.
+
+FP64: relative error of the total <= 1e-10 (and every block term within
+1e-10 of its own magnitude scale); FP32 covariance/Cholesky with FP64
+accumulation: <= 1e-4.  The oracle and the GPU consume the same structure
+through the import boundary.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from helpers import block_tolerance, problem, to_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sbv():
+    from paper_2504_12004_amd import sbv as S
+    return S
+
+
+def _check(sbv, X, y, th, S, two_nu, prec, tol):
+    ref, lb_ref = O.sbv_loglik(X, y, S, th, two_nu, blocks=True)
+    B = to_gpu(sbv, X, y, S)
+    got = sbv.sbv_loglik(B, th, two_nu, prec)[0]
+    lb = sbv.sbv_blocks_terms(B)
+    print(f"ref {ref!r} got {got!r} rel {abs(got - ref) / abs(ref):.3e}", flush=True)
+    assert abs(got - ref) <= tol * abs(ref)
+    assert np.all(np.abs(lb - lb_ref) <= block_tolerance(lb_ref, tol * (10 if prec else 1)))
+    B.free()
+    return got
+
+
+@pytest.mark.parametrize("two_nu", [1, 3, 5, 7])
+def test_fp64_small_blocks(sbv, two_nu):
+    X, y, th, S = problem(1500, 4, K=100, m=30, seed=21, two_nu=two_nu, tau2=1e-3)
+    _check(sbv, X, y, th, S, two_nu, sbv.SBV_FP64, 1e-10)
+
+
+def test_fp64_all_variants(sbv):
+    # joint sizes from 1 up to ~250 cover every kernel variant and ragged tails
+    X, y, th, S = problem(6000, 10, K=300, m=230, seed=22, tau2=1e-4, max_bs=30)
+    sizes = np.diff(S.nn_ptr) + np.diff(S.block_ptr)
+    assert sizes.max() > 192 and sizes.min() < 64
+    _check(sbv, X, y, th, S, 5, sbv.SBV_FP64, 1e-10)
+
+
+def test_fp64_small_workload(sbv):
+    """The n = 20,000, d = 10, Matern-5/2, 1,000-block, m = 60 workload at the true theta."""
+    from paper_2504_12004_amd import synth
+    w = synth.dataset("small_fp64")
+    X, th, xi = w["X"], w["theta"], w["xi"]
+    bb = np.exp(th[:10])
+    Sg = O.build(X, bb, K=1000, m=120, lloyd_iters=1, seed=12345)
+    y = O.sample(X, Sg, th, 5, xi)
+    S = O.build(X, bb, K=1000, m=60, lloyd_iters=10, seed=0)
+    _check(sbv, X, y, th, S, 5, sbv.SBV_FP64, 1e-10)
+
+
+def test_fp32_matches_within_1e4(sbv):
+    X, y, th, S = problem(6000, 10, K=300, m=200, seed=23, tau2=1e-4)
+    _check(sbv, X, y, th, S, 5, sbv.SBV_FP32, 1e-4)
+
+
+def test_single_block_and_no_conditioning(sbv):
+    X, y, th, S = problem(200, 3, K=1, m=0, seed=24, tau2=1e-2)
+    got = _check(sbv, X, y, th, S, 5, sbv.SBV_FP64, 1e-10)
+    assert abs(got - O.exact_loglik(X, y, th, 5)) < 1e-10 * abs(got)
+    X, y, th, S = problem(800, 3, K=60, m=0, seed=25, tau2=1e-2)
+    _check(sbv, X, y, th, S, 5, sbv.SBV_FP64, 1e-10)
+
+
+def test_full_conditioning_equals_exact(sbv):
+    X, y, th, S = problem(250, 3, K=12, m=250, seed=26, tau2=1e-3)
+    B = to_gpu(sbv, X, y, S)
+    got = sbv.sbv_loglik(B, th, 5)[0]
+    ex = O.exact_loglik(X, y, th, 5)
+    assert abs(got - ex) < 1e-10 * abs(ex)
