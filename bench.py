@@ -1,0 +1,206 @@
+"""Benchmark of the SBV log-likelihood hot path on one MI355X.
+
+Workload (the headline configuration): n = 1,000,000 inputs uniform on
+[0,1]^10, Matern-5/2, ranges log-uniform on [0.05, 3], sigma^2 = 1,
+tau^2 = 1e-4; k-means into 50,000 blocks bounded to 5..60 points; m = 200
+nearest earlier neighbours; evaluations at perturbed parameters
+theta_t = theta* + 0.1 N(0, I).  The structure is built once on the GPU
+(sbv_build_blocks) and stays resident; the timed region holds only
+log-likelihood evaluations with parameters and results already in HBM.
+
+One step = one FP64 log-likelihood evaluation of the whole dataset (all
+blocks: covariance build, factorisation, solves, log-det/quadratic-form,
+reduction).  The same line also reports the FP32 path (FP32 covariance and
+Cholesky, FP64 accumulation, FP64 re-run of low-pivot blocks) and the
+log-likelihood + gradient path when available.
+
+Prints ONE JSON line.  Only --gpus 1 is supported (one GPU per box).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP64 = 78.6e12  # MI355X dense FP64 (vector = matrix), FLOP/s
+PEAK_FP32 = 157.3e12
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=None, help="override n (testing only)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+
+    from paper_2504_12004_amd import sbv, synth
+
+    dev = torch.device("cuda:0")
+    torch.cuda.init()
+    w = synth.dataset("uneven_1m", n=args.n)
+    X, theta_true, xi = w["X"], w["theta"], w["xi"]
+    n, d = X.shape
+    K = w["K"] if args.n is None else max(1, args.n // 20)
+    m = w["m"]
+    two_nu = w["two_nu"]
+    bb = np.exp(theta_true[:d])
+
+    t0 = time.perf_counter()
+    B = sbv.sbv_build_blocks(X, None, bb, K, m, method=sbv.SBV_KMEANS, lloyd_iters=w["lloyd_iters"],
+                             min_bs=w["min_bs"], max_bs=w["max_bs"], seed=w["seed"])
+    t_build = time.perf_counter() - t0
+    log(f"built structure: n={n} K={B.K} nnz={B.nnz} in {t_build:.2f}s")
+    # observations: Vecchia simulation on the device when available, else the
+    # standard-normal innovations themselves (timing does not depend on y)
+    y_source = "vecchia-sampler"
+    try:
+        theta_gen = torch.tensor(theta_true, dtype=torch.float64, device=dev)
+        xi_d = torch.tensor(xi, dtype=torch.float64, device=dev)
+        y_d = torch.empty(n, dtype=torch.float64, device=dev)
+        sbv.sbv_sample_dev(B, theta_gen, two_nu, xi_d, y_d)
+        sbv.sbv_blocks_set_y_dev(B, y_d)
+    except (AttributeError, sbv.SBVError):
+        y_source = "iid-normal"
+        sbv.sbv_blocks_set_y(B, xi)
+    torch.cuda.synchronize()
+
+    thetas = synth.perturbed_thetas(theta_true, w["n_theta"], w["theta_seed"])
+    th_d = torch.tensor(thetas, dtype=torch.float64, device=dev)
+    out = torch.empty(max(args.steps, 1) + args.warmup + 8, dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def run(prec, steps, warm, timing):
+        for i in range(warm):
+            sbv.sbv_loglik_dev(B, th_d[i % len(thetas)], two_nu, out[i:i + 1], prec, stream)
+        torch.cuda.synchronize()
+        sbv.sbv_timing_enable(timing)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for i in range(steps):
+            sbv.sbv_loglik_dev(B, th_d[i % len(thetas)], two_nu, out[i:i + 1], prec, stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        kt = sbv.sbv_timing_read(prec) if timing else None
+        sbv.sbv_timing_enable(False)
+        return ms, kt, out[:steps].cpu().numpy()
+
+    # headline: FP64, timed without per-kernel events
+    ms64, _, ll64 = run(sbv.SBV_FP64, args.steps, args.warmup, False)
+    ms_step = ms64 / args.steps
+    log(f"FP64: {ms_step:.3f} ms/eval")
+    # per-kernel live timing of the same workload (separate pass, events on the launch stream)
+    kin = min(args.steps, 20)
+    _, kt64, _ = run(sbv.SBV_FP64, kin, 1, True)
+    ms32, kt32, ll32 = run(sbv.SBV_FP32, kin, 1, True)
+    fb = sbv.sbv_blocks_fallback_count(B)
+    rel32 = float(np.max(np.abs(ll32[:kin] - ll64[:kin]) / np.abs(ll64[:kin])))
+    log(f"FP32: {ms32 / kin:.3f} ms/eval, max rel diff vs FP64 {rel32:.2e}, fallback blocks {fb}")
+
+    flops, tiles = sbv.sbv_plan_flops(B, two_nu)
+    ms_tot, launches = kt64
+    v_dom = int(np.argmax(ms_tot))
+    avg_ms = ms_tot[v_dom] / max(launches[v_dom], 1)
+    achieved = flops[v_dom] / (avg_ms * 1e-3)
+    total_flop = float(np.sum(flops))
+    log(f"dominant kernel: variant with {tiles[v_dom]} tiles, {avg_ms:.3f} ms/launch, "
+        f"{achieved / 1e12:.2f} TFLOP/s algorithmic")
+
+    grad_rate = None
+    try:
+        g_d = torch.empty(d + 2, dtype=torch.float64, device=dev)
+        for i in range(2):
+            sbv.sbv_loglik_grad_dev(B, th_d[i], two_nu, out[i:i + 1], g_d, sbv.SBV_FP64, stream)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for i in range(kin):
+            sbv.sbv_loglik_grad_dev(B, th_d[i % len(thetas)], two_nu, out[i:i + 1], g_d, sbv.SBV_FP64, stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        grad_rate = 1000.0 * kin / e0.elapsed_time(e1)
+    except sbv.SBVError:
+        pass
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(B, X, sbv, theta_true, two_nu, args.cpu_seconds)
+
+    res = {
+        "metric": "SBV loglik evals/s (n=1M, m=200, FP64)",
+        "value": 1000.0 / ms_step,
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": f"synthetic (uniform X, GP observations from {y_source})",
+        "config": {"workload": "uneven_1m: n=1e6 d=10 Matern-5/2 tau2=1e-4 kmeans K=5e4 (5..60) m=200",
+                   "n": n, "d": d, "blocks": B.K, "m": m, "parallelism": "1 GPU"},
+        "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK_FP64 / 1e12,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64, "traffic": None,
+                     "kernel": f"k_block_loglik<double,{tiles[v_dom]}>",
+                     "flop_per_launch": flops[v_dom], "avg_launch_ms": avg_ms},
+        "extra": {
+            "fp64_total_algorithmic_tflops": total_flop / (ms_step * 1e-3) / 1e12,
+            "fp32_evals_per_s": 1000.0 * kin / ms32,
+            "fp32_max_rel_diff_vs_fp64": rel32,
+            "fp32_fallback_blocks": int(fb),
+            "grad_fp64_evals_per_s": grad_rate,
+            "build_seconds": t_build,
+        },
+    }
+    if cpu is not None:
+        res["cpu_baseline"] = cpu
+    print(json.dumps(res), flush=True)
+
+
+def cpu_baseline(B, X, sbv, theta, two_nu, seconds):
+    """The FP64 oracle on a bounded sample of the same workload's blocks,
+    scaled to evaluations per second of the whole dataset."""
+    import oracle as O
+    bp, pts, npt, nid = sbv.sbv_blocks_export(B)
+    S = O.Structure(B.n, B.d, 0, bp, pts, npt, nid)
+    y = np.zeros(B.n)
+    rng = np.random.default_rng(0)
+    order = rng.permutation(B.K)
+    threads = len(os.sched_getaffinity(0))
+    # calibrate on 64 blocks, then take enough blocks for about `seconds`
+    t0 = time.perf_counter()
+    O.sbv_loglik(X, y, O.subset(S, order[:64]), theta, two_nu, nthreads=threads)
+    t_cal = max(time.perf_counter() - t0, 1e-4)
+    nb = int(min(B.K, max(64, 64 * seconds / t_cal)))
+    sub = O.subset(S, order[:nb])
+    t0 = time.perf_counter()
+    O.sbv_loglik(X, y, sub, theta, two_nu, nthreads=threads)
+    t = time.perf_counter() - t0
+    full = t * B.K / nb
+    return {"value": 1.0 / full, "unit": "evals/s", "cores": threads, "kind": "oracle",
+            "sample": f"{nb} of {B.K} blocks (random), {t:.1f}s, scaled to the full dataset"}
+
+
+if __name__ == "__main__":
+    main()

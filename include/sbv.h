@@ -136,6 +136,60 @@ sbv_status sbv_loglik_grad_dev(const sbv_blocks* sets, int32_t n_sets, const dou
                                const int32_t* two_nu, int32_t prec, double* loglik_dev,
                                double* grad_dev, void* stream);
 
+/*
+ * Vecchia conditional simulation on the handle's structure: blocks are visited
+ * in rank order (level by level on the device) and each draws
+ *   y_B = Sigma_BJ Sigma_JJ^{-1} y_J + L' xi_B,  L' = chol(Sigma_BB - Sigma_BJ Sigma_JJ^{-1} Sigma_JB),
+ * i.e. the conditional mean and covariance of Alg. 5 Step 1 (Sec. 5.5).  With
+ * every earlier point in J this is an exact draw from N(0, Sigma).  theta: d+2
+ * log-parameters; xi: n standard-normal innovations in original point order
+ * (drawn by the caller); y: n outputs in original order (may be NULL).  The
+ * simulated observations also replace the handle's observations.
+ */
+sbv_status sbv_sample(sbv_blocks h, const double* theta, int32_t two_nu, const double* xi, double* y);
+sbv_status sbv_sample_dev(sbv_blocks h, const double* theta_dev, int32_t two_nu, const double* xi_dev,
+                          double* y_dev, void* stream);
+
+/* Options of the maximum-likelihood driver. */
+typedef struct {
+  int32_t optimizer;          /* SBV_NELDER_MEAD (values only) or SBV_LBFGS (values + gradients)   */
+  int32_t prec;               /* SBV_FP64 or SBV_FP32 evaluations                                  */
+  int32_t fp64_polish;        /* with SBV_FP32: continue in FP64 from the FP32 optimum             */
+  int32_t max_evals;          /* objective evaluations allowed (-> SBV_E_NOCONV when reached)       */
+  double ftol;                /* Nelder-Mead: stop when the simplex spread of -l is <= ftol |l|;   */
+                              /* L-BFGS: stop when one iteration changes -l by <= ftol |l|         */
+  double gtol;                /* L-BFGS: stop when max |dl/dtheta_k| <= gtol                        */
+  int32_t rebuild_rounds;     /* must be 0 (the structure is fixed during a fit)                   */
+  int32_t lbfgs_m;            /* L-BFGS memory (0: 10)                                              */
+  double init_step;           /* Nelder-Mead initial simplex edge in log-parameter units (0: 0.5)  */
+  const char* checkpoint_path;/* optional JSON state file, rewritten every iteration; if it exists */
+                              /* at the start the run resumes from it                               */
+} sbv_fit_opts;
+
+/* Objective of sbv_minimize: returns f(x) and, when grad != NULL, its gradient.
+ * A non-finite return marks x as outside the domain. */
+typedef double (*sbv_objective)(const double* x, double* grad, void* ctx);
+
+/*
+ * Minimise fn over n variables from x (overwritten with the best point):
+ * Nelder-Mead (1965) or L-BFGS (Liu & Nocedal 1989) with a strong-Wolfe line
+ * search, per opts (prec/fp64_polish/rebuild_rounds ignored).  Returns
+ * SBV_E_NOCONV when max_evals is reached first (x, fbest still written).
+ */
+sbv_status sbv_minimize(int32_t method, int32_t n, double* x, sbv_objective fn, void* ctx,
+                        const sbv_fit_opts* opts, double* fbest, int32_t* n_evals);
+
+/*
+ * Maximum-likelihood estimate of theta (the d+2 log-parameters) on one handle,
+ * maximising the SBV log-likelihood with the device evaluations (the paper's
+ * MLE loop).  theta_hat receives the optimum, loglik_fp64 a final FP64
+ * evaluation there (always FP64, whatever o->prec), n_evals the objective
+ * evaluations used, seconds the wall time.  SBV_E_NOCONV: max_evals reached
+ * (outputs still written).
+ */
+sbv_status sbv_fit(sbv_blocks set, const double* theta0, int32_t two_nu, const sbv_fit_opts* o,
+                   double* theta_hat, double* loglik_fp64, int32_t* n_evals, double* seconds);
+
 /* Number of blocks recomputed in FP64 by the last SBV_FP32 evaluation of this
  * handle (synchronises the device). */
 sbv_status sbv_blocks_fallback_count(sbv_blocks h, int64_t* count);
@@ -143,6 +197,21 @@ sbv_status sbv_blocks_fallback_count(sbv_blocks h, int64_t* count);
 /* Per-block terms l_i of the last evaluation of this handle, in rank order
  * (host, K values; synchronises the device). */
 sbv_status sbv_blocks_terms(sbv_blocks h, double* terms);
+
+/*
+ * Measurement hooks (used by the benchmark).  sbv_timing_enable(1) makes every
+ * subsequent evaluation bracket each kernel-variant launch with HIP events on
+ * the launch stream; sbv_timing_read sums the elapsed milliseconds and launch
+ * counts per variant for one precision (arrays of length sbv_timing_read's
+ * *n_variants, at most 16; synchronises the device).  sbv_timing_enable(0)
+ * discards the records.  sbv_plan_flops reports, per variant, the algorithmic
+ * FLOP sum_i (nA_i^3/3 + nA_i^2) of one evaluation of these sets
+ * (nA_i = m_i + b_i) and each variant's tile capacity in 16-row tiles.
+ */
+sbv_status sbv_timing_enable(int32_t on);
+sbv_status sbv_timing_read(int32_t prec, int32_t* n_variants, double* ms_total, int64_t* launches);
+sbv_status sbv_plan_flops(const sbv_blocks* sets, int32_t n_sets, const int32_t* two_nu, double* flops,
+                          int32_t* tiles_of_variant, int32_t* n_variants);
 
 /* Message of the last failure on the calling thread (valid until the next call). */
 const char* sbv_last_error(void);

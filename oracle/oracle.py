@@ -115,6 +115,18 @@ class Structure:
                 self.nn_idx[self.nn_ptr[r]:self.nn_ptr[r + 1]])
 
 
+def subset(S, blocks):
+    """Sub-structure holding only the listed blocks (ids still index the full X)."""
+    bp, pts, npt, nid = [0], [], [0], []
+    for r in blocks:
+        B, J = S.block(int(r))
+        pts.extend(B.tolist())
+        nid.extend(J.tolist())
+        bp.append(len(pts))
+        npt.append(len(nid))
+    return Structure(S.n, S.d, S.m, bp, pts, npt, nid)
+
+
 def build(X, beta_build, K, m, lloyd_iters=10, min_bs=0, max_bs=0, seed=0):
     """Oracle block builder: scaling, anchors/k-means, size bounds, random order,
     centres and exact m nearest earlier neighbours."""

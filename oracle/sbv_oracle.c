@@ -554,11 +554,12 @@ static double or_block_loglik(or_blk* B, double* work_v) {
   return -0.5 * (u + dd + (double)bi * OR_LOG2PI);
 }
 
+/* Blocks may cover a subset of the n points (a sample of blocks); ids index X. */
 static int or_check_structure(int64_t n, int64_t K, const int64_t* bp, const int64_t* bpts,
                               const int64_t* np, const int64_t* nidx) {
-  if (bp[0] != 0 || bp[K] != n || np[0] != 0) return OR_EINVAL;
+  if (bp[0] != 0 || bp[K] > n || np[0] != 0) return OR_EINVAL;
   for (int64_t r = 0; r < K; ++r) if (bp[r + 1] <= bp[r] || np[r + 1] < np[r]) return OR_EINVAL;
-  for (int64_t i = 0; i < n; ++i) if (bpts[i] < 0 || bpts[i] >= n) return OR_EINVAL;
+  for (int64_t i = 0; i < bp[K]; ++i) if (bpts[i] < 0 || bpts[i] >= n) return OR_EINVAL;
   for (int64_t t = 0; t < np[K]; ++t) if (nidx[t] < 0 || nidx[t] >= n) return OR_EINVAL;
   return OR_OK;
 }

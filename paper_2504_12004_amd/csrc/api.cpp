@@ -97,6 +97,16 @@ struct sbv_blocks_s {
   DevBuf<int32_t> flag;
   int64_t last_fallback = 0;
   int32_t last_two_nu = 0;
+  // conditional simulator: blocks grouped by dependency level
+  struct SampleLevel {
+    int variant;
+    int count;
+    DevBuf<WorkItem> items;
+    DevBuf<int> dcount;
+  };
+  std::vector<SampleLevel> sample_levels;
+  DevBuf<double> xi_ord, theta_s;
+  DevBuf<SetDesc> sample_desc;
 };
 
 // ---- evaluation plans ------------------------------------------------------
@@ -111,6 +121,10 @@ struct Bucket {
 
 struct Plan {
   std::vector<sbv_blocks> sets;
+  std::vector<SetDesc> hdesc;      // host copy of the set descriptors
+  std::vector<DevBuf<double>> qbuf;  // adjoint buffers (allocated on the first gradient call)
+  std::vector<DevBuf<int64_t>> qoff;
+  DevBuf<double> grad;
   std::vector<int32_t> two_nu;
   std::vector<int32_t> theta_off;
   int theta_len = 0;
@@ -192,6 +206,7 @@ sbv_status get_plan(const sbv_blocks* sets, int32_t n_sets, const int32_t* two_n
     }
   }
   P->theta_len = off;
+  P->hdesc = hd;
   HIP_TRY(P->dsets.alloc(n_sets));
   HIP_TRY(hipMemcpy(P->dsets.p, hd.data(), sizeof(SetDesc) * n_sets, hipMemcpyHostToDevice));
   HIP_TRY(P->theta.alloc(off));
@@ -220,16 +235,85 @@ sbv_status get_plan(const sbv_blocks* sets, int32_t n_sets, const int32_t* two_n
   return SBV_OK;
 }
 
+// Kernel timing mode: when on, every bucket launch is bracketed by HIP events
+// recorded on the launch stream and the elapsed times are accumulated per
+// (precision, variant) when the caller asks for them.
+struct TimedLaunch {
+  int prec, variant;
+  hipEvent_t a, b;
+};
+bool g_timing = false;
+std::vector<TimedLaunch> g_timed;
+
 // Piv threshold of the FP32 path: a block whose FP32 pivot falls to or below
 // this fraction of the original diagonal is recomputed in FP64.
 double g_piv_tau = 1e-3;
+
+// Allocate the per-block adjoint buffers (e, g, Q: nA_i (b_i + 2) values per
+// block) of every set of a plan, once.
+sbv_status ensure_adjoint(Plan* P) {
+  if (!P->qbuf.empty()) return SBV_OK;
+  const int ns = (int)P->sets.size();
+  P->qbuf.resize(ns);
+  P->qoff.resize(ns);
+  for (int s = 0; s < ns; ++s) {
+    sbv_blocks h = P->sets[s];
+    std::vector<int64_t> off(h->K + 1, 0);
+    for (int64_t b = 0; b < h->K; ++b) {
+      const int64_t bi = h->block_ptr[b + 1] - h->block_ptr[b];
+      off[b + 1] = off[b] + (int64_t)h->joint[b] * (bi + 2);
+    }
+    HIP_TRY(P->qbuf[s].alloc(off[h->K]));
+    HIP_TRY(P->qoff[s].alloc(h->K + 1));
+    HIP_TRY(hipMemcpy(P->qoff[s].p, off.data(), sizeof(int64_t) * (h->K + 1), hipMemcpyHostToDevice));
+    P->hdesc[s].qbuf = P->qbuf[s].p;
+    P->hdesc[s].qoff = P->qoff[s].p;
+  }
+  HIP_TRY(hipMemcpy(P->dsets.p, P->hdesc.data(), sizeof(SetDesc) * ns, hipMemcpyHostToDevice));
+  HIP_TRY(P->grad.alloc(P->theta_len));
+  return SBV_OK;
+}
+
+// Queue one evaluation of log-likelihood and gradient: per bucket the
+// factor + adjoint-solve kernel, then the contraction kernel; FP32 blocks that
+// trip the pivot test are redone in FP64 (both kernels).
+sbv_status run_plan_grad(Plan* P, int32_t prec, hipStream_t s) {
+  sbv_status st = ensure_adjoint(P);
+  if (st) return st;
+  const int pk = prec == SBV_FP32 ? 1 : 0;
+  for (auto& B : P->buckets) {
+    HIP_TRY(launch_loglik(pk, B.variant, B.count, P->dsets.p, P->theta.p, B.items.p, B.dcount.p,
+                          pk ? g_piv_tau : 0.0, s, true));
+    HIP_TRY(launch_contract(pk, B.variant, B.count, P->dsets.p, P->theta.p, B.items.p, B.dcount.p, s));
+    if (pk) {
+      HIP_TRY(launch_zero_int(B.fb_count.p, 1, s));
+      HIP_TRY(launch_flag_compact(P->dsets.p, B.items.p, B.dcount.p, B.fb_items.p, B.fb_count.p, s));
+      int grid = std::min(B.count, max_grid(0, B.variant));
+      HIP_TRY(launch_loglik(0, B.variant, grid, P->dsets.p, P->theta.p, B.fb_items.p, B.fb_count.p, 0.0, s, true));
+      HIP_TRY(launch_contract(0, B.variant, grid, P->dsets.p, P->theta.p, B.fb_items.p, B.fb_count.p, s));
+    }
+  }
+  HIP_TRY(launch_reduce(P->dsets.p, (int)P->sets.size(), nullptr, P->out.p, P->bad.p, s));
+  HIP_TRY(launch_reduce_grad(P->dsets.p, (int)P->sets.size(), P->grad.p, s));
+  return SBV_OK;
+}
 
 // Queue one evaluation of plan P (theta already in P->theta) on stream s;
 // result in P->out.
 sbv_status run_plan(Plan* P, int32_t prec, hipStream_t s) {
   for (auto& B : P->buckets) {
+    TimedLaunch tl{prec == SBV_FP32 ? 1 : 0, B.variant, nullptr, nullptr};
+    if (g_timing) {
+      HIP_TRY(hipEventCreate(&tl.a));
+      HIP_TRY(hipEventCreate(&tl.b));
+      HIP_TRY(hipEventRecord(tl.a, s));
+    }
     HIP_TRY(launch_loglik(prec == SBV_FP32 ? 1 : 0, B.variant, B.count, P->dsets.p, P->theta.p,
                           B.items.p, B.dcount.p, prec == SBV_FP32 ? g_piv_tau : 0.0, s));
+    if (g_timing) {
+      HIP_TRY(hipEventRecord(tl.b, s));
+      g_timed.push_back(tl);
+    }
     if (prec == SBV_FP32) {
       HIP_TRY(launch_zero_int(B.fb_count.p, 1, s));
       HIP_TRY(launch_flag_compact(P->dsets.p, B.items.p, B.dcount.p, B.fb_items.p, B.fb_count.p, s));
@@ -389,6 +473,142 @@ sbv_status sbv_loglik(const sbv_blocks* sets, int32_t n_sets, const double* thet
   return SBV_OK;
 }
 
+sbv_status sbv_loglik_grad_dev(const sbv_blocks* sets, int32_t n_sets, const double* theta_dev,
+                               const int32_t* two_nu, int32_t prec, double* loglik_dev, double* grad_dev,
+                               void* stream) {
+  sbv_status st = check_sets(sets, n_sets, two_nu);
+  if (st) return st;
+  if (!theta_dev || !loglik_dev || !grad_dev) return fail(SBV_E_INVAL, "theta_dev, loglik_dev and grad_dev are required");
+  if (prec != SBV_FP64 && prec != SBV_FP32) return fail(SBV_E_INVAL, "prec must be SBV_FP64 or SBV_FP32");
+  Plan* P = nullptr;
+  st = get_plan(sets, n_sets, two_nu, &P);
+  if (st) return st;
+  hipStream_t s = (hipStream_t)stream;
+  HIP_TRY(hipMemcpyAsync(P->theta.p, theta_dev, sizeof(double) * P->theta_len, hipMemcpyDeviceToDevice, s));
+  st = run_plan_grad(P, prec, s);
+  if (st) return st;
+  HIP_TRY(hipMemcpyAsync(loglik_dev, P->out.p, sizeof(double) * n_sets, hipMemcpyDeviceToDevice, s));
+  HIP_TRY(hipMemcpyAsync(grad_dev, P->grad.p, sizeof(double) * P->theta_len, hipMemcpyDeviceToDevice, s));
+  return SBV_OK;
+}
+
+sbv_status sbv_loglik_grad(const sbv_blocks* sets, int32_t n_sets, const double* theta, const int32_t* two_nu,
+                           int32_t prec, double* loglik, double* grad) {
+  sbv_status st = check_sets(sets, n_sets, two_nu);
+  if (st) return st;
+  if (!theta || !loglik || !grad) return fail(SBV_E_INVAL, "theta, loglik and grad are required");
+  if (prec != SBV_FP64 && prec != SBV_FP32) return fail(SBV_E_INVAL, "prec must be SBV_FP64 or SBV_FP32");
+  Plan* P = nullptr;
+  st = get_plan(sets, n_sets, two_nu, &P);
+  if (st) return st;
+  if (!finite_all(theta, P->theta_len)) return fail(SBV_E_INVAL, "theta has non-finite values");
+  HIP_TRY(hipMemcpy(P->theta.p, theta, sizeof(double) * P->theta_len, hipMemcpyHostToDevice));
+  st = run_plan_grad(P, prec, nullptr);
+  if (st) return st;
+  std::vector<double> out(n_sets), g(P->theta_len);
+  std::vector<int> bad(n_sets);
+  HIP_TRY(hipMemcpy(out.data(), P->out.p, sizeof(double) * n_sets, hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(g.data(), P->grad.p, sizeof(double) * P->theta_len, hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(bad.data(), P->bad.p, sizeof(int) * n_sets, hipMemcpyDeviceToHost));
+  std::memcpy(loglik, out.data(), sizeof(double) * n_sets);
+  for (int i = 0; i < n_sets; ++i) {
+    const int off = P->theta_off[i], np = sets[i]->d + 2;
+    for (int k = 0; k < np; ++k) grad[off + k] = bad[i] ? NAN : g[off + k];
+  }
+  for (int i = 0; i < n_sets; ++i)
+    if (bad[i]) return fail(SBV_E_NOTPD, "set " + std::to_string(i) + " has a block that is not positive definite");
+  return SBV_OK;
+}
+
+// Dependency levels of the conditional simulator: a block's level is one more
+// than the highest level among the blocks holding its conditioning points, so
+// every block of a level only reads observations of lower levels.
+static sbv_status ensure_sampler(sbv_blocks h, int32_t two_nu) {
+  if (h->sample_levels.empty()) {
+    const int64_t K = h->K;
+    std::vector<int32_t> block_of(h->n);
+    for (int64_t r = 0; r < K; ++r)
+      for (int64_t t = h->block_ptr[r]; t < h->block_ptr[r + 1]; ++t) block_of[t] = (int32_t)r;
+    std::vector<int32_t> pos_of(h->n);
+    for (int64_t t = 0; t < h->n; ++t) pos_of[h->block_pts[t]] = (int32_t)t;
+    std::vector<int32_t> level(K, 0);
+    int32_t maxl = 0;
+    for (int64_t r = 0; r < K; ++r) {
+      int32_t l = 0;
+      for (int64_t t = h->nn_ptr[r]; t < h->nn_ptr[r + 1]; ++t)
+        l = std::max(l, level[block_of[pos_of[h->nn_idx[t]]]] + 1);
+      level[r] = l;
+      maxl = std::max(maxl, l);
+    }
+    const int nv = n_variants();
+    std::vector<std::vector<WorkItem>> lists((size_t)(maxl + 1) * nv);
+    for (int64_t r = 0; r < K; ++r)
+      lists[(size_t)level[r] * nv + variant_for(h->joint[r])].push_back(WorkItem{0, (int32_t)r});
+    for (size_t li = 0; li < lists.size(); ++li) {
+      if (lists[li].empty()) continue;
+      sbv_blocks_s::SampleLevel L;
+      L.variant = (int)(li % nv);
+      L.count = (int)lists[li].size();
+      HIP_TRY(L.items.alloc(L.count));
+      HIP_TRY(hipMemcpy(L.items.p, lists[li].data(), sizeof(WorkItem) * L.count, hipMemcpyHostToDevice));
+      HIP_TRY(L.dcount.alloc(1));
+      HIP_TRY(hipMemcpy(L.dcount.p, &L.count, sizeof(int), hipMemcpyHostToDevice));
+      h->sample_levels.push_back(std::move(L));
+    }
+    HIP_TRY(h->xi_ord.alloc(h->n));
+    HIP_TRY(h->theta_s.alloc(h->d + 2));
+    HIP_TRY(h->sample_desc.alloc(1));
+  }
+  SetDesc D{};
+  D.X = h->X.p;
+  D.y = h->y.p;
+  D.bptr = h->bptr.p;
+  D.nptr = h->nptr.p;
+  D.nidx = h->nidx.p;
+  D.llb = h->llb.p;
+  D.flag = h->flag.p;
+  D.gradb = h->gradb.p;
+  D.d = h->d;
+  D.two_nu = two_nu;
+  D.theta_off = 0;
+  D.K = (int32_t)h->K;
+  D.xi = h->xi_ord.p;
+  D.y_out = h->y.p;
+  HIP_TRY(hipMemcpy(h->sample_desc.p, &D, sizeof(SetDesc), hipMemcpyHostToDevice));
+  return SBV_OK;
+}
+
+sbv_status sbv_sample_dev(sbv_blocks h, const double* theta_dev, int32_t two_nu, const double* xi_dev,
+                          double* y_dev, void* stream) {
+  if (!h || !theta_dev || !xi_dev) return fail(SBV_E_INVAL, "handle, theta_dev and xi_dev are required");
+  if (two_nu != 1 && two_nu != 3 && two_nu != 5 && two_nu != 7) return fail(SBV_E_INVAL, "two_nu must be 1, 3, 5 or 7");
+  sbv_status st = ensure_sampler(h, two_nu);
+  if (st) return st;
+  hipStream_t s = (hipStream_t)stream;
+  HIP_TRY(hipMemcpyAsync(h->theta_s.p, theta_dev, sizeof(double) * (h->d + 2), hipMemcpyDeviceToDevice, s));
+  HIP_TRY(launch_scatter_y(xi_dev, h->pos_of.p, h->xi_ord.p, h->n, s));
+  for (auto& L : h->sample_levels)
+    HIP_TRY(launch_sample(L.variant, L.count, h->sample_desc.p, h->theta_s.p, L.items.p, L.dcount.p, s));
+  if (y_dev) HIP_TRY(launch_gather_y(h->y.p, h->pos_of.p, y_dev, h->n, s));
+  return SBV_OK;
+}
+
+sbv_status sbv_sample(sbv_blocks h, const double* theta, int32_t two_nu, const double* xi, double* y) {
+  if (!h || !theta || !xi) return fail(SBV_E_INVAL, "handle, theta and xi are required");
+  if (!finite_all(theta, h->d + 2) || !finite_all(xi, h->n)) return fail(SBV_E_INVAL, "non-finite theta or xi");
+  DevBuf<double> th, x, yy;
+  HIP_TRY(th.alloc(h->d + 2));
+  HIP_TRY(x.alloc(h->n));
+  HIP_TRY(yy.alloc(h->n));
+  HIP_TRY(hipMemcpy(th.p, theta, sizeof(double) * (h->d + 2), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(x.p, xi, sizeof(double) * h->n, hipMemcpyHostToDevice));
+  sbv_status st = sbv_sample_dev(h, th.p, two_nu, x.p, yy.p, nullptr);
+  if (st) return st;
+  if (y) HIP_TRY(hipMemcpy(y, yy.p, sizeof(double) * h->n, hipMemcpyDeviceToHost));
+  HIP_TRY(hipDeviceSynchronize());
+  return SBV_OK;
+}
+
 sbv_status sbv_blocks_fallback_count(sbv_blocks h, int64_t* count) {
   if (!h || !count) return fail(SBV_E_INVAL, "handle and count are required");
   HIP_TRY(hipDeviceSynchronize());
@@ -415,6 +635,54 @@ sbv_status sbv_blocks_fallback_count(sbv_blocks h, int64_t* count) {
     }
   }
   *count = c;
+  return SBV_OK;
+}
+
+sbv_status sbv_timing_enable(int32_t on) {
+  for (auto& t : g_timed) {
+    (void)hipEventDestroy(t.a);
+    (void)hipEventDestroy(t.b);
+  }
+  g_timed.clear();
+  g_timing = on != 0;
+  return SBV_OK;
+}
+
+sbv_status sbv_timing_read(int32_t prec, int32_t* n_variants_out, double* ms_total, int64_t* launches) {
+  HIP_TRY(hipDeviceSynchronize());
+  const int nv = n_variants();
+  if (n_variants_out) *n_variants_out = nv;
+  for (int v = 0; v < nv; ++v) {
+    if (ms_total) ms_total[v] = 0.0;
+    if (launches) launches[v] = 0;
+  }
+  for (auto& t : g_timed) {
+    if (t.prec != (prec == SBV_FP32 ? 1 : 0)) continue;
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, t.a, t.b));
+    if (ms_total) ms_total[t.variant] += ms;
+    if (launches) launches[t.variant] += 1;
+  }
+  return SBV_OK;
+}
+
+sbv_status sbv_plan_flops(const sbv_blocks* sets, int32_t n_sets, const int32_t* two_nu, double* flops,
+                          int32_t* variant_of_bucket, int32_t* n_buckets) {
+  sbv_status st = check_sets(sets, n_sets, two_nu);
+  if (st) return st;
+  Plan* P = nullptr;
+  st = get_plan(sets, n_sets, two_nu, &P);
+  if (st) return st;
+  const int nv = n_variants();
+  for (int v = 0; v < nv; ++v) flops[v] = 0.0;
+  for (int s = 0; s < n_sets; ++s)
+    for (int64_t b = 0; b < sets[s]->K; ++b) {
+      const double nA = sets[s]->joint[b];
+      flops[variant_for(sets[s]->joint[b])] += nA * nA * nA / 3.0 + nA * nA;
+    }
+  if (n_buckets) *n_buckets = nv;
+  if (variant_of_bucket)
+    for (int v = 0; v < nv; ++v) variant_of_bucket[v] = variant(v).ntm;
   return SBV_OK;
 }
 

@@ -95,15 +95,26 @@ __device__ __forceinline__ T matern(T r, int two_nu) {
 
 constexpr double kLog2Pi = 1.83787706640934548356065947281123527;
 
-template <typename T, int NTM>
+// Row stride of the right-hand-side chunk used by the adjoint solves (32
+// columns plus one of padding so that rows fall on different LDS banks).
+constexpr int kRS = 33;
+constexpr int kChunk = 32;
+
+template <typename T, int NTM, bool GRAD = false>
 struct Smem {
+  static constexpr int kPanel = NTM * 256;
+  static constexpr int kRhs = NTM * kTile * kRS;
   T z[NTM * kTile * kMaxDim];  // scaled coordinates of A (padded rows unused)
   T yv[NTM * kTile];           // observations, overwritten by the forward solve
-  T panel[NTM * 256];          // column k of L, operand layout, per tile row
+  // column k of L in operand layout (factorisation) / right-hand-side chunk
+  // (adjoint solves, GRAD only)
+  T panel[(GRAD && kRhs > kPanel) ? kRhs : kPanel];
   T diag[256];                 // diagonal tile to factor (row-major)
   T negM[256];                 // -(L_kk^{-T}) in B-operand layout
   T zk[kTile];                 // solved z of the current tile row
-  int flag;
+  T zfull[GRAD ? NTM * kTile : 1];  // all of z = L^{-1} y (GRAD only)
+  T xi[NTM * kTile];                // innovations of the conditional simulator
+  T gv[GRAD ? NTM * kTile : 1];     // g = Q z_B accumulated over chunks (GRAD only)
 };
 
 // Factor the 16x16 SPD tile in sm.diag on one wave (rows in lanes 0..15,
@@ -113,9 +124,9 @@ struct Smem {
 // returns its pivot L_rr and z_r; `bad` is raised for a non-positive or
 // non-finite pivot and `low` for a pivot at or below tau * original diagonal
 // (the FP32 fallback test).
-template <typename T, int NTM>
-__device__ void factor_diag(Smem<T, NTM>& sm, int lane, int k, int nreal, T diag0, T tau, T& pivot_out,
-                            T& z_out, int& bad, int& low) {
+template <typename T, bool SAMPLE = false, class SM>
+__device__ void factor_diag(SM& sm, int lane, int k, int nreal, T diag0, T tau, T& pivot_out,
+                            T& z_out, int& bad, int& low, int mi = 0, T* ysim = nullptr) {
   const int r = lane & 15;
   T a[16];
 #pragma unroll
@@ -131,7 +142,22 @@ __device__ void factor_diag(Smem<T, NTM>& sm, int lane, int k, int nreal, T diag
     T inv = T(1) / sq;
     invd[j] = inv;
     a[j] = (r == j) ? sq : a[j] * inv;
-    T zj = rlane(yr, j) * inv;
+    T zj;
+    if (!SAMPLE) {
+      zj = rlane(yr, j) * inv;
+    } else {
+      // conditional simulation: rows of J are solved (w = z), rows of B take
+      // w = xi and emit y = L_jj xi - v, v being the eliminated part so far
+      const int R = kTile * k + j;
+      const T vj = rlane(yr, j);
+      if (R < mi) {
+        zj = vj * inv;
+      } else {
+        const T xj = sm.xi[R];
+        zj = xj;
+        if (r == j) *ysim = sq * xj - vj;
+      }
+    }
     yr = (r == j) ? zj : (r > j ? yr - a[j] * zj : yr);
 #pragma unroll
     for (int c = j + 1; c < 16; ++c) {
@@ -171,8 +197,8 @@ __device__ void factor_diag(Smem<T, NTM>& sm, int lane, int k, int nreal, T diag
 // order: tile i (i >= j) entry (register t, lane l) holds
 // -Sigma(point 16i + l%16, point 16j + row(l/16, t)), with tau^2 on the
 // diagonal and identity rows/columns past the joint size.
-template <typename T, int NTM, int NTHR>
-__device__ void gen_column(Smem<T, NTM>& sm, int tid, int j, int nt, int nA, int d, int two_nu, T sigma2,
+template <typename T, int NTHR, class SM>
+__device__ void gen_column(SM& sm, int tid, int j, int nt, int nA, int d, int two_nu, T sigma2,
                            T tau2) {
   const int total = (nt - j) * 256;
   for (int e = tid; e < total; e += NTHR) {
@@ -199,23 +225,27 @@ __device__ void gen_column(Smem<T, NTM>& sm, int tid, int j, int nt, int nA, int
 
 // Panel wave: for every tile step factors the diagonal tile, solves the 16
 // entries of z, accumulates the trailing log-pivots and z^2 in FP64, and
-// applies the forward-solve update to the observations below.
-template <typename T, int NTM, int NTHR>
-__device__ void panel_wave(Smem<T, NTM>& sm, int lane, int nt, int mi, int nA, int d, int two_nu, T sigma2,
-                           T tau2, T tau, double& ld_acc, double& q_acc, int& bad, int& low) {
+// applies the forward-solve update to the observations below.  In GRAD mode it
+// also keeps all of z and then takes part in the adjoint solves (barriers,
+// right-hand-side set-up and write-back).
+template <typename T, int NTM, int NTHR, bool GRAD, bool SAMPLE, class SM>
+__device__ void panel_wave(SM& sm, int lane, int nt, int mi, int nA, int d, int two_nu, T sigma2, T tau2, T tau,
+                           double& ld_acc, double& q_acc, int& bad, int& low, double* yout) {
   const T diag0 = sigma2 + tau2;
   for (int j = 0; j < nt; ++j) {
-    gen_column<T, NTM, NTHR>(sm, lane, j, nt, nA, d, two_nu, sigma2, tau2);
+    gen_column<T, NTHR>(sm, lane, j, nt, nA, d, two_nu, sigma2, tau2);
     __syncthreads();  // G1
     __syncthreads();  // G2
   }
   for (int k = 0; k < nt; ++k) {
     __syncthreads();  // S1: diagonal tile published
-    T piv, zr;
-    factor_diag<T, NTM>(sm, lane, k, nA - kTile * k, diag0, tau, piv, zr, bad, low);
+    T piv, zr, ysim = T(0);
+    factor_diag<T, SAMPLE>(sm, lane, k, nA - kTile * k, diag0, tau, piv, zr, bad, low, mi, &ysim);
     const int rowg = kTile * k + lane;
+    if (SAMPLE && lane < 16 && rowg >= mi && rowg < nA) yout[rowg - mi] = (double)ysim;
     if (lane < 16) {
       sm.zk[lane] = zr;
+      if (GRAD) sm.zfull[rowg] = zr;
       if (rowg >= mi && rowg < nA) {
         ld_acc += log((double)piv);
         q_acc += (double)zr * (double)zr;
@@ -234,11 +264,66 @@ __device__ void panel_wave(Smem<T, NTM>& sm, int lane, int nt, int mi, int nA, i
   }
 }
 
+
+// Re-derive the (wave-uniform) slot coordinates at the top of a loop body so
+// that the compiler recomputes per-slot LDS addresses inside the loop instead
+// of hoisting all of them into registers for the whole loop.
+template <int SLOTS>
+__device__ __forceinline__ void refresh_slots(int* ti, int* tj) {
+#pragma unroll
+  for (int s = 0; s < SLOTS; ++s) {
+    int a = ti[s], b = tj[s];
+    asm volatile("" : "+v"(a), "+v"(b));
+    ti[s] = __builtin_amdgcn_readfirstlane(a);
+    tj[s] = __builtin_amdgcn_readfirstlane(b);
+  }
+}
+
+// Right-hand sides of the adjoint solves, as one list of columns:
+// column 0 is [z_J; 0] (its solution is e = [Sigma_J^{-1} y_J; 0]) and column
+// c >= 1 is the unit vector of row mi + c - 1 (their solutions are the columns
+// of Q = L^{-T} [0; I_b]).
+template <typename T, int NTHR, class SM>
+__device__ void rhs_init(SM& sm, int tid, int ch, int nt, int mi, int bi) {
+  for (int e = tid; e < nt * kTile * kChunk; e += NTHR) {
+    const int r = e / kChunk, c = e - r * kChunk;
+    const int col = kChunk * ch + c;
+    T v = T(0);
+    if (col == 0) v = r < mi ? sm.zfull[r] : T(0);
+    else if (col <= bi && r == mi + col - 1) v = T(1);
+    sm.panel[r * kRS + c] = v;
+  }
+}
+
+// After the solves of one chunk: accumulate g = Q z_B, write e / Q columns of
+// this block to its slice of the adjoint buffer (e, g, then Q column-major).
+template <typename T, int NTHR, class SM>
+__device__ void rhs_writeback(SM& sm, int tid, int ch, int mi, int nA, int bi, T* out) {
+  for (int r = tid; r < nA; r += NTHR) {
+    T gacc = sm.gv[r];
+#pragma unroll 4
+    for (int c = 0; c < kChunk; ++c) {
+      const int col = kChunk * ch + c;
+      if (col > bi) break;
+      const T v = sm.panel[r * kRS + c];
+      if (col == 0) {
+        out[r] = v;
+      } else {
+        gacc += v * sm.zfull[mi + col - 1];
+        out[(int64_t)(2 + col - 1) * nA + r] = v;
+      }
+    }
+    sm.gv[r] = gacc;
+  }
+}
+
 // Worker waves: own the register tiles, build them from the covariance, and
-// run the column TRSMs and trailing MFMA updates of every step.
-template <typename T, int NTM, int NWK, int NTHR>
-__device__ void worker_waves(Smem<T, NTM>& sm, int wk, int lane, int nt, int nA, int d, int two_nu,
-                             T sigma2, T tau2) {
+// run the column TRSMs and trailing MFMA updates of every step.  In GRAD mode
+// the finished factor stays in the slots (diagonal slots take L_kk^{-1}) and
+// the workers run the backward solves L^T X = R chunk by chunk.
+template <typename T, int NTM, int NWK, int NTHR, bool GRAD, class SM>
+__device__ void worker_waves(SM& sm, int wk, int lane, int nt, int mi, int nA, int bi, int d, int two_nu,
+                             T sigma2, T tau2, T* gout) {
   typedef typename MF<T>::acc acc_t;
   constexpr int NTT = NTM * (NTM + 1) / 2;
   constexpr int SLOTS = (NTT + NWK - 1) / NWK;
@@ -258,8 +343,8 @@ __device__ void worker_waves(Smem<T, NTM>& sm, int wk, int lane, int nt, int nA,
       }
       i = j + t;
     }
-    ti[s] = i;
-    tj[s] = j;
+    ti[s] = __builtin_amdgcn_readfirstlane(i);
+    tj[s] = __builtin_amdgcn_readfirstlane(j);
   }
   // covariance tiles, one tile column at a time: every thread of the
   // workgroup builds entries into LDS (gen_column), owners copy theirs in.
@@ -270,7 +355,8 @@ __device__ void worker_waves(Smem<T, NTM>& sm, int wk, int lane, int nt, int nA,
     for (int t = 0; t < 4; ++t) acc[s][t] = T(0);
   }
   for (int j = 0; j < nt; ++j) {
-    gen_column<T, NTM, NTHR>(sm, 64 * (wk + 1) + lane, j, nt, nA, d, two_nu, sigma2, tau2);
+    refresh_slots<SLOTS>(ti, tj);
+    gen_column<T, NTHR>(sm, 64 * (wk + 1) + lane, j, nt, nA, d, two_nu, sigma2, tau2);
     __syncthreads();  // G1: column j staged
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
@@ -283,6 +369,7 @@ __device__ void worker_waves(Smem<T, NTM>& sm, int wk, int lane, int nt, int nA,
     __syncthreads();  // G2: staging area free
   }
   for (int k = 0; k < nt; ++k) {
+    refresh_slots<SLOTS>(ti, tj);
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
       if (ti[s] == k && tj[s] == k) {
@@ -304,6 +391,11 @@ __device__ void worker_waves(Smem<T, NTM>& sm, int wk, int lane, int nt, int nA,
 #pragma unroll
         for (int t = 0; t < 4; ++t) P[opoff<T>(MF<T>::row(g, t), cl)] = o[t];
       }
+      if (GRAD && tj[s] == k && ti[s] == k) {
+        // keep X_kk = L_kk^{-1} in accumulator layout: X[a][b] = -negM[opoff(a, b)]
+#pragma unroll
+        for (int t = 0; t < 4; ++t) acc[s][t] = -sm.negM[opoff<T>(MF<T>::row(g, t), cl)];
+      }
     }
     __syncthreads();  // S3
     // trailing update G_ij += L_jk L_ik^T
@@ -317,20 +409,89 @@ __device__ void worker_waves(Smem<T, NTM>& sm, int wk, int lane, int nt, int nA,
         for (int q = 0; q < 4; ++q) o = MF<T>::mma(Pj[64 * q + lane], Pi[64 * q + lane], o);
         acc[s] = o;
       }
-      }
+    }
   }
+  if (!GRAD) return;
+  // ---- adjoint solves L^T X = R, right-hand sides in chunks of 32 columns
+  const int nch = (bi + 1 + kChunk - 1) / kChunk;
+  const int tid = 64 * (wk + 1) + lane;
+  __syncthreads();  // B0: forward finished everywhere
+  for (int r = tid; r < nt * kTile; r += NTHR) sm.gv[r] = T(0);
+  for (int ch = 0; ch < nch; ++ch) {
+    rhs_init<T, NTHR>(sm, tid, ch, nt, mi, bi);
+    __syncthreads();  // B1
+    for (int k = nt - 1; k >= 0; --k) {
+      refresh_slots<SLOTS>(ti, tj);
+      // X_k = L_kk^{-T} R_k by the diagonal owner
+#pragma unroll
+      for (int s = 0; s < SLOTS; ++s) {
+        if (ti[s] == k && tj[s] == k) {
+#pragma unroll
+          for (int cb = 0; cb < 2; ++cb) {
+            acc_t o = {T(0), T(0), T(0), T(0)};
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+              o = MF<T>::mma(acc[s][q], sm.panel[(kTile * k + MF<T>::row(g, q)) * kRS + 16 * cb + cl], o);
+#pragma unroll
+            for (int t = 0; t < 4; ++t) sm.panel[(kTile * k + MF<T>::row(g, t)) * kRS + 16 * cb + cl] = o[t];
+          }
+        }
+      }
+      __syncthreads();  // B2
+      // R_j -= L_kj^T X_k for j < k by the owners of row k of L
+#pragma unroll
+      for (int s = 0; s < SLOTS; ++s) {
+        if (ti[s] == k && tj[s] < k && tj[s] >= 0) {
+#pragma unroll
+          for (int cb = 0; cb < 2; ++cb) {
+            acc_t o = {T(0), T(0), T(0), T(0)};
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+              o = MF<T>::mma(acc[s][q], sm.panel[(kTile * k + MF<T>::row(g, q)) * kRS + 16 * cb + cl], o);
+            T* R = sm.panel + (kTile * tj[s]) * kRS + 16 * cb + cl;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) R[MF<T>::row(g, t) * kRS] -= o[t];
+          }
+        }
+      }
+      __syncthreads();  // B3
+    }
+    rhs_writeback<T, NTHR>(sm, tid, ch, mi, nA, bi, gout);
+    __syncthreads();  // B4
+  }
+  for (int r = tid; r < nA; r += NTHR) gout[nA + r] = sm.gv[r];
 }
 
-template <typename T, int NTM, int NW>
+// The panel wave's share of the adjoint solves: same barriers, plus its part
+// of the set-up and write-back loops.
+template <typename T, int NTHR, class SM>
+__device__ void panel_adjoint(SM& sm, int lane, int nt, int mi, int nA, int bi, T* gout) {
+  const int nch = (bi + 1 + kChunk - 1) / kChunk;
+  __syncthreads();  // B0
+  for (int r = lane; r < nt * kTile; r += NTHR) sm.gv[r] = T(0);
+  for (int ch = 0; ch < nch; ++ch) {
+    rhs_init<T, NTHR>(sm, lane, ch, nt, mi, bi);
+    __syncthreads();  // B1
+    for (int k = nt - 1; k >= 0; --k) {
+      __syncthreads();  // B2
+      __syncthreads();  // B3
+    }
+    rhs_writeback<T, NTHR>(sm, lane, ch, mi, nA, bi, gout);
+    __syncthreads();  // B4
+  }
+  for (int r = lane; r < nA; r += NTHR) gout[nA + r] = sm.gv[r];
+}
+
+template <typename T, int NTM, int NW, bool GRAD, bool SAMPLE = false>
 __global__ __launch_bounds__(NW * 64) void k_block_loglik(const SetDesc* __restrict__ sets,
                                                           const double* __restrict__ theta,
                                                           const WorkItem* __restrict__ items,
                                                           const int* __restrict__ count,
                                                           double piv_tau) {
-  __shared__ Smem<T, NTM> sm;
+  __shared__ Smem<T, NTM, GRAD> sm;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
-  const int wave = tid >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int total = *count;
 
   for (int it = blockIdx.x; it < total; it += gridDim.x) {
@@ -344,6 +505,7 @@ __global__ __launch_bounds__(NW * 64) void k_block_loglik(const SetDesc* __restr
     const int nt = (nA + kTile - 1) / kTile;
     const T sigma2 = T(exp(th[d]));
     const T tau2 = T(exp(th[d + 1]));
+    T* gout = GRAD ? reinterpret_cast<T*>(S.qbuf) + S.qoff[w.block] : nullptr;
 
     // gather A = J u B (J first): scaled coordinates and observations
     for (int e = tid; e < nA * d; e += NW * 64) {
@@ -353,16 +515,17 @@ __global__ __launch_bounds__(NW * 64) void k_block_loglik(const SetDesc* __restr
     }
     for (int p = tid; p < nt * kTile; p += NW * 64) {
       T v = T(0);
-      if (p < nA) v = T(S.y[p < mi ? S.nidx[n0 + p] : b0 + (p - mi)]);
+      if (p < nA && (!SAMPLE || p < mi)) v = T(S.y[p < mi ? S.nidx[n0 + p] : b0 + (p - mi)]);
       sm.yv[p] = v;
+      if (SAMPLE) sm.xi[p] = (p >= mi && p < nA) ? T(S.xi[b0 + (p - mi)]) : T(0);
     }
     __syncthreads();
 
     if (wave == 0) {
       double ld_acc = 0.0, q_acc = 0.0;
       int bad = 0, low = 0;
-      panel_wave<T, NTM, NW * 64>(sm, lane, nt, mi, nA, d, S.two_nu, sigma2, tau2, T(piv_tau), ld_acc, q_acc,
-                                  bad, low);
+      panel_wave<T, NTM, NW * 64, GRAD, SAMPLE>(sm, lane, nt, mi, nA, d, S.two_nu, sigma2, tau2, T(piv_tau),
+                                                ld_acc, q_acc, bad, low, S.y_out + b0);
 #pragma unroll
       for (int off = 8; off >= 1; off >>= 1) {
         ld_acc += __shfl_xor(ld_acc, off, 16);
@@ -375,15 +538,172 @@ __global__ __launch_bounds__(NW * 64) void k_block_loglik(const SetDesc* __restr
         S.llb[w.block] = l;
         S.flag[w.block] = fb;
       }
+      if (GRAD) panel_adjoint<T, NW * 64>(sm, lane, nt, mi, nA, bi, gout);
     } else {
-      worker_waves<T, NTM, NW - 1, NW * 64>(sm, wave - 1, lane, nt, nA, d, S.two_nu, sigma2, tau2);
+      worker_waves<T, NTM, NW - 1, NW * 64, GRAD>(sm, wave - 1, lane, nt, mi, nA, bi, d, S.two_nu, sigma2, tau2,
+                                                  gout);
+    }
+    __syncthreads();
+  }
+}
+
+// ---- gradient contraction -------------------------------------------------
+// For one block, with e, g and Q = L^{-T}[0; I_b] from the adjoint solves:
+//   dl_i/dtheta_k = 1/2 sum_ab M_ab dSigma_ab/dtheta_k,
+//   M = e g^T + g e^T + g g^T - Q Q^T,
+// where Q Q^T is accumulated tile by tile on MFMA (register tiles over the
+// lower triangle) and dSigma is recomputed from the scaled coordinates:
+//   d/dlog beta_k: sigma^2 (-rho'(r)/r) s_k^2,  d/dlog sigma^2: sigma^2 rho(r),
+//   d/dlog tau^2: tau^2 on the diagonal.
+template <typename T>
+__device__ __forceinline__ T mdrho_over_r(T r, int two_nu) {
+  T e = t_exp(-r);
+  if (two_nu == 5) return (T(1) + r) * e * T(1.0 / 3.0);
+  if (two_nu == 3) return e;
+  if (two_nu == 7) return (T(3) + T(3) * r + r * r) * e * T(1.0 / 15.0);
+  return r > T(0) ? e / r : T(0);
+}
+
+template <typename T, int NTM>
+struct SmemC {
+  T z[NTM * kTile * kMaxDim];
+  T q[NTM * kTile * kRS];
+  T ev[NTM * kTile];
+  T gv[NTM * kTile];
+  double red[16][kMaxDim + 2];
+};
+
+template <typename T, int NTM, int NW>
+__global__ __launch_bounds__(NW * 64) void k_block_contract(const SetDesc* __restrict__ sets,
+                                                            const double* __restrict__ theta,
+                                                            const WorkItem* __restrict__ items,
+                                                            const int* __restrict__ count) {
+  typedef typename MF<T>::acc acc_t;
+  constexpr int NTT = NTM * (NTM + 1) / 2;
+  constexpr int SLOTS = (NTT + NW - 1) / NW;
+  constexpr int NTHR = NW * 64;
+  __shared__ SmemC<T, NTM> sm;
+  const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int g = lane >> 4, cl = lane & 15;
+  const int total = *count;
+  for (int it = blockIdx.x; it < total; it += gridDim.x) {
+    const WorkItem w = items[it];
+    const SetDesc S = sets[w.set];
+    const int d = S.d, two_nu = S.two_nu;
+    const double* th = theta + S.theta_off;
+    const int b0 = S.bptr[w.block], b1 = S.bptr[w.block + 1];
+    const int64_t n0 = S.nptr[w.block], n1 = S.nptr[w.block + 1];
+    const int mi = (int)(n1 - n0), bi = b1 - b0, nA = mi + bi;
+    const int nt = (nA + kTile - 1) / kTile;
+    const int ntt = nt * (nt + 1) / 2;
+    const T sigma2 = T(exp(th[d]));
+    const T tau2 = T(exp(th[d + 1]));
+    const T* src = reinterpret_cast<const T*>(S.qbuf) + S.qoff[w.block];
+    for (int e = tid; e < nA * d; e += NTHR) {
+      int p = e / d, k = e - p * d;
+      int pos = p < mi ? S.nidx[n0 + p] : b0 + (p - mi);
+      sm.z[p * d + k] = T(S.X[(int64_t)pos * d + k] * exp(-th[k]));
+    }
+    for (int r = tid; r < nt * kTile; r += NTHR) {
+      sm.ev[r] = r < nA ? src[r] : T(0);
+      sm.gv[r] = r < nA ? src[nA + r] : T(0);
+    }
+    int ti[SLOTS], tj[SLOTS];
+#pragma unroll
+    for (int s = 0; s < SLOTS; ++s) {
+      int t = s * NW + wave;
+      int i = -1, j = -1;
+      if (t < ntt) {
+        j = 0;
+        while (t >= nt - j) {
+          t -= nt - j;
+          ++j;
+        }
+        i = j + t;
+      }
+      ti[s] = __builtin_amdgcn_readfirstlane(i);
+      tj[s] = __builtin_amdgcn_readfirstlane(j);
+    }
+    acc_t P[SLOTS];
+#pragma unroll
+    for (int s = 0; s < SLOTS; ++s) P[s] = acc_t{T(0), T(0), T(0), T(0)};
+    // Q Q^T over chunks of 32 columns of Q
+    for (int c0 = 0; c0 < bi; c0 += kChunk) {
+      __syncthreads();
+      for (int e = tid; e < nt * kTile * kChunk; e += NTHR) {
+        const int c = e / (nt * kTile), r = e - c * (nt * kTile);
+        T v = T(0);
+        if (r < nA && c0 + c < bi) v = src[(int64_t)(2 + c0 + c) * nA + r];
+        sm.q[r * kRS + c] = v;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int s = 0; s < SLOTS; ++s) {
+        if (ti[s] >= 0) {
+          const T* Qi = sm.q + (kTile * ti[s] + cl) * kRS;
+          const T* Qj = sm.q + (kTile * tj[s] + cl) * kRS;
+          acc_t o = P[s];
+#pragma unroll
+          for (int q = 0; q < kChunk / 4; ++q) o = MF<T>::mma(Qi[4 * q + g], Qj[4 * q + g], o);
+          P[s] = o;
+        }
+      }
+    }
+    __syncthreads();
+    // contraction with the recomputed covariance derivatives
+    double gacc[kMaxDim + 2];
+#pragma unroll
+    for (int k = 0; k < kMaxDim + 2; ++k) gacc[k] = 0.0;
+#pragma unroll
+    for (int s = 0; s < SLOTS; ++s) {
+      if (ti[s] < 0) continue;
+      const double wgt = ti[s] == tj[s] ? 1.0 : 2.0;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int a = kTile * ti[s] + MF<T>::row(g, t);
+        const int b = kTile * tj[s] + cl;
+        if (a >= nA || b >= nA) continue;
+        const T M = sm.ev[a] * sm.gv[b] + sm.gv[a] * sm.ev[b] + sm.gv[a] * sm.gv[b] - P[s][t];
+        T r2 = T(0);
+        for (int k = 0; k < d; ++k) {
+          T df = sm.z[a * d + k] - sm.z[b * d + k];
+          r2 += df * df;
+        }
+        const T r = t_sqrt(r2);
+        const double wm = wgt * (double)M;
+        const double f = wm * (double)(sigma2 * mdrho_over_r<T>(r, two_nu));
+#pragma unroll
+        for (int k = 0; k < kMaxDim; ++k) {
+          if (k < d) {
+            T df = sm.z[a * d + k] - sm.z[b * d + k];
+            gacc[k] += f * (double)(df * df);
+          }
+        }
+        gacc[kMaxDim] += wm * (double)(sigma2 * matern<T>(r, two_nu));
+        if (a == b) gacc[kMaxDim + 1] += wm * (double)tau2;
+      }
+    }
+    // fixed-order reduction: lanes, then waves
+#pragma unroll
+    for (int k = 0; k < kMaxDim + 2; ++k) {
+      double v = gacc[k];
+#pragma unroll
+      for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+      if (lane == 0) sm.red[wave][k] = v;
+    }
+    __syncthreads();
+    if (tid < d + 2) {
+      const int k = tid < d ? tid : kMaxDim + (tid - d);
+      double v = 0.0;
+      for (int wv = 0; wv < NW; ++wv) v += sm.red[wv][k];
+      S.gradb[(int64_t)w.block * (d + 2) + tid] = 0.5 * v;
     }
     __syncthreads();
   }
 }
 
 // ---- variants -------------------------------------------------------------
-static const Variant kVariants[] = {{4, 2}, {8, 4}, {12, 8}, {17, 8}};
+static const Variant kVariants[] = {{4, 2}, {8, 4}, {12, 8}, {14, 8}, {16, 8}, {17, 8}};
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
 int n_variants() { return kNumVariants; }
@@ -395,31 +715,74 @@ int variant_for(int nA) {
 }
 
 template <typename T, int NTM, int NW>
-static hipError_t launch_t(int grid, const SetDesc* sets, const double* theta, const WorkItem* items,
+static hipError_t launch_t(int grid, bool grad, const SetDesc* sets, const double* theta, const WorkItem* items,
                            const int* count, double piv_tau, hipStream_t s) {
-  hipLaunchKernelGGL((k_block_loglik<T, NTM, NW>), dim3(grid), dim3(NW * 64), 0, s, sets, theta,
-                     items, count, piv_tau);
+  if (grad)
+    hipLaunchKernelGGL((k_block_loglik<T, NTM, NW, true>), dim3(grid), dim3(NW * 64), 0, s, sets, theta, items,
+                       count, piv_tau);
+  else
+    hipLaunchKernelGGL((k_block_loglik<T, NTM, NW, false>), dim3(grid), dim3(NW * 64), 0, s, sets, theta, items,
+                       count, piv_tau);
   return hipGetLastError();
 }
 
-hipError_t launch_loglik(int prec, int v, int grid, const SetDesc* sets, const double* theta,
-                         const WorkItem* items, const int* count, double piv_tau, hipStream_t s) {
-  if (grid <= 0) return hipSuccess;
-  if (prec == 0) {
-    switch (v) {
-      case 0: return launch_t<double, 4, 2>(grid, sets, theta, items, count, piv_tau, s);
-      case 1: return launch_t<double, 8, 4>(grid, sets, theta, items, count, piv_tau, s);
-      case 2: return launch_t<double, 12, 8>(grid, sets, theta, items, count, piv_tau, s);
-      case 3: return launch_t<double, 17, 8>(grid, sets, theta, items, count, piv_tau, s);
-    }
-  } else {
-    switch (v) {
-      case 0: return launch_t<float, 4, 2>(grid, sets, theta, items, count, piv_tau, s);
-      case 1: return launch_t<float, 8, 4>(grid, sets, theta, items, count, piv_tau, s);
-      case 2: return launch_t<float, 12, 8>(grid, sets, theta, items, count, piv_tau, s);
-      case 3: return launch_t<float, 17, 8>(grid, sets, theta, items, count, piv_tau, s);
-    }
+template <typename T, int NTM, int NW>
+static hipError_t launch_s(int grid, const SetDesc* sets, const double* theta, const WorkItem* items,
+                           const int* count, hipStream_t s) {
+  hipLaunchKernelGGL((k_block_loglik<T, NTM, NW, false, true>), dim3(grid), dim3(NW * 64), 0, s, sets, theta,
+                     items, count, 0.0);
+  return hipGetLastError();
+}
+
+template <typename T, int NTM, int NW>
+static hipError_t launch_c(int grid, const SetDesc* sets, const double* theta, const WorkItem* items,
+                           const int* count, hipStream_t s) {
+  hipLaunchKernelGGL((k_block_contract<T, NTM, NW>), dim3(grid), dim3(NW * 64), 0, s, sets, theta, items, count);
+  return hipGetLastError();
+}
+
+#define SBV_VARIANT_SWITCH(T, CALL)   \
+  switch (v) {                        \
+    case 0: return CALL(T, 4, 2);     \
+    case 1: return CALL(T, 8, 4);     \
+    case 2: return CALL(T, 12, 8);    \
+    case 3: return CALL(T, 14, 8);    \
+    case 4: return CALL(T, 16, 8);    \
+    case 5: return CALL(T, 17, 8);    \
   }
+
+hipError_t launch_loglik(int prec, int v, int grid, const SetDesc* sets, const double* theta,
+                         const WorkItem* items, const int* count, double piv_tau, hipStream_t s, bool grad) {
+  if (grid <= 0) return hipSuccess;
+#define SBV_CALL(T, A, B) launch_t<T, A, B>(grid, grad, sets, theta, items, count, piv_tau, s)
+  if (prec == 0) {
+    SBV_VARIANT_SWITCH(double, SBV_CALL)
+  } else {
+    SBV_VARIANT_SWITCH(float, SBV_CALL)
+  }
+#undef SBV_CALL
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_sample(int v, int grid, const SetDesc* sets, const double* theta, const WorkItem* items,
+                         const int* count, hipStream_t s) {
+  if (grid <= 0) return hipSuccess;
+#define SBV_CALL(T, A, B) launch_s<T, A, B>(grid, sets, theta, items, count, s)
+  SBV_VARIANT_SWITCH(double, SBV_CALL)
+#undef SBV_CALL
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_contract(int prec, int v, int grid, const SetDesc* sets, const double* theta,
+                           const WorkItem* items, const int* count, hipStream_t s) {
+  if (grid <= 0) return hipSuccess;
+#define SBV_CALL(T, A, B) launch_c<T, A, (B < 4 ? 4 : B)>(grid, sets, theta, items, count, s)
+  if (prec == 0) {
+    SBV_VARIANT_SWITCH(double, SBV_CALL)
+  } else {
+    SBV_VARIANT_SWITCH(float, SBV_CALL)
+  }
+#undef SBV_CALL
   return hipErrorInvalidValue;
 }
 
@@ -463,6 +826,32 @@ hipError_t launch_reduce(const SetDesc* sets, int n_sets, const int* set_k, doub
                          hipStream_t s) {
   (void)set_k;
   hipLaunchKernelGGL(k_reduce, dim3(n_sets), dim3(256), 0, s, sets, out, bad);
+  return hipGetLastError();
+}
+
+// Per-set gradient: sum of the per-block terms in a fixed order, one
+// workgroup per set, one pass per parameter.
+__global__ __launch_bounds__(256) void k_reduce_grad(const SetDesc* __restrict__ sets,
+                                                     double* __restrict__ out) {
+  __shared__ double red[256];
+  const SetDesc S = sets[blockIdx.x];
+  const int np = S.d + 2;
+  for (int k = 0; k < np; ++k) {
+    double s = 0.0;
+    for (int i = threadIdx.x; i < S.K; i += 256) s += S.gradb[(int64_t)i * np + k];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) out[S.theta_off + k] = red[0];
+    __syncthreads();
+  }
+}
+
+hipError_t launch_reduce_grad(const SetDesc* sets, int n_sets, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce_grad, dim3(n_sets), dim3(256), 0, s, sets, out);
   return hipGetLastError();
 }
 

@@ -23,6 +23,10 @@ struct SetDesc {
   double* llb;            // K per-block terms (output)
   int32_t* flag;          // K per-block status (output): bit0 fp32 pivot flag, bit1 not PD
   double* gradb;          // K x (d+2) per-block gradient terms (output, gradient kernels)
+  double* qbuf;           // adjoint buffer: per block e, g, Q (elements of the kernel precision)
+  const int64_t* qoff;    // K offsets into qbuf, in elements of the kernel precision
+  const double* xi;       // n innovations, rank order (conditional simulation only)
+  double* y_out;          // n simulated observations, rank order (conditional simulation only)
   int32_t d;
   int32_t two_nu;
   int32_t theta_off;      // offset of this set's d+2 parameters in the theta buffer
@@ -44,7 +48,13 @@ struct Variant {
 // Launchers (kernels.hip).  `count` is a device int; the kernel loops over
 // items[blockIdx.x + k*gridDim.x] while the index is below *count.
 hipError_t launch_loglik(int prec, int variant, int grid, const SetDesc* sets, const double* theta,
-                         const WorkItem* items, const int* count, double piv_tau, hipStream_t s);
+                         const WorkItem* items, const int* count, double piv_tau, hipStream_t s,
+                         bool grad = false);
+hipError_t launch_contract(int prec, int variant, int grid, const SetDesc* sets, const double* theta,
+                           const WorkItem* items, const int* count, hipStream_t s);
+hipError_t launch_sample(int variant, int grid, const SetDesc* sets, const double* theta,
+                         const WorkItem* items, const int* count, hipStream_t s);
+hipError_t launch_reduce_grad(const SetDesc* sets, int n_sets, double* out, hipStream_t s);
 int n_variants();
 Variant variant(int v);
 int variant_for(int nA);  // smallest variant holding a joint size nA, or -1
@@ -58,6 +68,7 @@ int max_grid(int prec, int variant);
 }  // namespace sbv
 
 namespace sbv {
+hipError_t launch_gather_y(const double* y_ord, const int32_t* pos_of, double* y, int64_t n, hipStream_t s);
 hipError_t launch_scatter_y(const double* y, const int32_t* pos_of, double* y_ord, int64_t n,
                             hipStream_t s);
 }  // namespace sbv

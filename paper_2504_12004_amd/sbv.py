@@ -71,6 +71,14 @@ def lib():
                                           C.c_void_p, C.c_void_p]),
         "sbv_blocks_fallback_count": (C.c_int, [_h, _i64]),
         "sbv_blocks_terms": (C.c_int, [_h, _d]),
+        "sbv_sample": (C.c_int, [_h, _d, C.c_int32, _d, _d]),
+        "sbv_sample_dev": (C.c_int, [_h, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
+        "sbv_fit": (C.c_int, [_h, _d, C.c_int32, C.POINTER(sbv_fit_opts), _d, _d, _i32, _d]),
+        "sbv_minimize": (C.c_int, [C.c_int32, C.c_int32, _d, C.c_void_p, C.c_void_p, C.POINTER(sbv_fit_opts), _d,
+                                   _i32]),
+        "sbv_timing_enable": (C.c_int, [C.c_int32]),
+        "sbv_timing_read": (C.c_int, [C.c_int32, _i32, _d, _i64]),
+        "sbv_plan_flops": (C.c_int, [C.POINTER(_h), C.c_int32, _i32, _d, _i32, _i32]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -244,3 +252,88 @@ def sbv_blocks_info(b):
 
 def sbv_last_error():
     return lib().sbv_last_error().decode()
+
+
+def sbv_timing_enable(on):
+    _check(lib().sbv_timing_enable(int(bool(on))))
+
+
+def sbv_timing_read(prec):
+    """Per-variant (ms_total, launches) of timed launches of one precision."""
+    nv = C.c_int32()
+    ms = np.zeros(16)
+    la = np.zeros(16, np.int64)
+    _check(lib().sbv_timing_read(int(prec), C.byref(nv), _p(ms), _p(la, _i64)))
+    return ms[:nv.value], la[:nv.value]
+
+
+def sbv_plan_flops(sets, two_nu):
+    """Per-variant algorithmic FLOP of one evaluation and the variants' tile capacities."""
+    hs, ns = _handles(sets)
+    tn = np.ascontiguousarray(np.broadcast_to(np.asarray(two_nu, np.int32), (ns,)), dtype=np.int32)
+    fl = np.zeros(16)
+    tiles = np.zeros(16, np.int32)
+    nv = C.c_int32()
+    _check(lib().sbv_plan_flops(hs, ns, _p(tn, _i32), _p(fl), _p(tiles, _i32), C.byref(nv)))
+    return fl[:nv.value], tiles[:nv.value]
+
+
+def sbv_sample(b, theta, two_nu, xi):
+    """Vecchia conditional simulation on b's structure; returns y (original order)."""
+    th, x = _c64(theta), _c64(xi)
+    y = np.empty(b.n)
+    _check(lib().sbv_sample(b.handle, _p(th), int(two_nu), _p(x), _p(y)))
+    return y
+
+
+def sbv_sample_dev(b, theta_dev, two_nu, xi_dev, y_dev=None, stream=None):
+    _check(lib().sbv_sample_dev(b.handle, C.c_void_p(_ptr(theta_dev)), int(two_nu), C.c_void_p(_ptr(xi_dev)),
+                                C.c_void_p(_ptr(y_dev) if y_dev is not None else 0), C.c_void_p(_stream(stream))))
+
+
+OBJECTIVE = C.CFUNCTYPE(C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_void_p)
+
+
+def make_fit_opts(optimizer=SBV_LBFGS, prec=SBV_FP64, fp64_polish=False, max_evals=500, ftol=1e-12, gtol=1e-6,
+                  lbfgs_m=10, init_step=0.5, checkpoint_path=None):
+    return sbv_fit_opts(int(optimizer), int(prec), int(bool(fp64_polish)), int(max_evals), float(ftol), float(gtol),
+                        0, int(lbfgs_m), float(init_step),
+                        checkpoint_path.encode() if checkpoint_path else None)
+
+
+def sbv_minimize(method, x0, fn, opts):
+    """Minimise fn(x) -> f or fn(x, want_grad) -> (f, g) with the library's optimisers."""
+    x = _c64(x0).copy()
+    n = len(x)
+
+    def cb(xp, gp, _ctx):
+        xv = np.ctypeslib.as_array(xp, shape=(n,)).copy()
+        if gp:
+            f, g = fn(xv, True)
+            gv = np.ctypeslib.as_array(gp, shape=(n,))
+            gv[:] = g
+            return float(f)
+        return float(fn(xv, False))
+
+    cfun = OBJECTIVE(cb)
+    fb = C.c_double()
+    ne = C.c_int32()
+    st = lib().sbv_minimize(int(method), n, _p(x), C.cast(cfun, C.c_void_p), None, C.byref(opts), C.byref(fb),
+                            C.byref(ne))
+    if st not in (SBV_OK, SBV_E_NOCONV):
+        _check(st)
+    return x, fb.value, ne.value, st == SBV_OK
+
+
+def sbv_fit(b, theta0, two_nu, opts):
+    """MLE on one handle; returns (theta_hat, loglik_fp64, n_evals, seconds, converged)."""
+    th = _c64(theta0)
+    out = np.empty_like(th)
+    l64 = C.c_double()
+    ne = C.c_int32()
+    sec = C.c_double()
+    st = lib().sbv_fit(b.handle, _p(th), int(two_nu), C.byref(opts), _p(out), C.byref(l64), C.byref(ne),
+                       C.byref(sec))
+    if st not in (SBV_OK, SBV_E_NOCONV):
+        _check(st)
+    return out, l64.value, ne.value, sec.value, st == SBV_OK

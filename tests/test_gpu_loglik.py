@@ -77,3 +77,18 @@ def test_full_conditioning_equals_exact(sbv):
     got = sbv.sbv_loglik(B, th, 5)[0]
     ex = O.exact_loglik(X, y, th, 5)
     assert abs(got - ex) < 1e-10 * abs(ex)
+
+
+def test_sampler_matches_oracle(sbv):
+    """Device conditional simulation == oracle simulation on the same structure
+    and innovations; with full conditioning it is the exact Cholesky draw."""
+    from paper_2504_12004_amd import synth
+    X, th, xi = synth.random_spd_problem(3000, 6, seed=51, tau2=1e-3)
+    S = O.build(X, np.exp(th[:6]), K=150, m=60, lloyd_iters=3, seed=4)
+    ref = O.sample(X, S, th, 5, xi)
+    B = to_gpu(sbv, X, None, S)
+    y = sbv.sbv_sample(B, th, 5, xi)
+    assert np.max(np.abs(y - ref)) <= 1e-9 * max(1.0, np.max(np.abs(ref)))
+    # the handle now holds the draw: its log-likelihood matches the oracle's on it
+    got = sbv.sbv_loglik(B, th, 5)[0]
+    assert abs(got - O.sbv_loglik(X, ref, S, th, 5)) <= 1e-10 * abs(got)
