@@ -190,6 +190,45 @@ sbv_status sbv_minimize(int32_t method, int32_t n, double* x, sbv_objective fn, 
 sbv_status sbv_fit(sbv_blocks set, const double* theta0, int32_t two_nu, const sbv_fit_opts* o,
                    double* theta_hat, double* loglik_fp64, int32_t* n_evals, double* seconds);
 
+/* ---- learned warm start ------------------------------------------------
+ * A fully connected FP32 network in -> hidden (x layers, GELU in its exact
+ * erf form) -> out, trained and run on the device by the library's own
+ * kernels (tiled GEMM with bias/GELU epilogues, GELU backward, MSE, Adam), that
+ * maps summary statistics of a dataset to a starting theta for sbv_fit.
+ * Parameters are packed layer by layer as W (outputs x inputs, row-major) then
+ * b; initialisation is He-normal from SplitMix64(seed).
+ */
+typedef struct sbv_mlp_s* sbv_mlp;
+
+sbv_status sbv_mlp_create(int32_t in, int32_t hidden, int32_t layers, int32_t out, uint64_t seed,
+                          sbv_mlp* h);
+void sbv_mlp_free(sbv_mlp h);
+int64_t sbv_mlp_num_params(sbv_mlp h);
+sbv_status sbv_mlp_get_params(sbv_mlp h, float* params);
+sbv_status sbv_mlp_set_params(sbv_mlp h, const float* params);
+/* Mean-squared-error loss of one batch (X: n x in, Y: n x out, host, used as
+ * given -- no standardisation) and its gradient (host, num_params floats). */
+sbv_status sbv_mlp_loss_grad(sbv_mlp h, const float* X, const float* Y, int32_t n, float* loss, float* grad);
+/* Adam (lr, beta1 0.9, beta2 0.999, eps 1e-8) on column-standardised X and Y
+ * (statistics kept in the handle) for `epochs` shuffled passes of `batch`
+ * rows; final_loss = mean batch loss of the last epoch (standardised units). */
+sbv_status sbv_mlp_train(sbv_mlp h, const float* X, const float* Y, int64_t n, int32_t epochs,
+                         int32_t batch, float lr, uint64_t seed, float* final_loss);
+/* Predictions for n rows of raw features (standardisation applied and undone). */
+sbv_status sbv_mlp_predict(sbv_mlp h, const float* X, int64_t n, float* Y);
+sbv_status sbv_mlp_save(sbv_mlp h, const char* path);
+sbv_status sbv_mlp_load(const char* path, sbv_mlp* h);
+/*
+ * Summary statistics of a dataset (4 + 5 (d + 2) values, 64 for d = 10) on a
+ * subsample of min(n, sub_n) points chosen by SplitMix64(seed): log var(y),
+ * log mean 1/2 (y_i - y_nn1(i))^2, and for the 1st, 2nd, 4th, 8th and 16th
+ * Euclidean neighbour the least-squares coefficients of the scaled
+ * semivariance 1/2 (y_i - y_j)^2 / var(y) on [1, dx_1^2 .. dx_d^2] with the
+ * fit's R^2, then d/10 and 1.  X row-major n x d, y n values, both host FP64.
+ */
+sbv_status sbv_features(const double* X, const double* y, int64_t n, int32_t d, int64_t sub_n, uint64_t seed,
+                        double* feat);
+
 /* Number of blocks recomputed in FP64 by the last SBV_FP32 evaluation of this
  * handle (synchronises the device). */
 sbv_status sbv_blocks_fallback_count(sbv_blocks h, int64_t* count);

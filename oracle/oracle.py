@@ -183,3 +183,44 @@ def sample(X, S, theta, two_nu, xi):
     if st != OR_OK:
         raise ValueError(f"oracle sample status {st}")
     return y
+
+
+def mlp_shapes(n_in, hidden, layers, n_out):
+    """Offsets of each layer's (W, b) in the packed parameter vector."""
+    offs, o, din = [], 0, n_in
+    for l in range(layers + 1):
+        dout = hidden if l < layers else n_out
+        offs.append((o, dout, din))
+        o += dout * din + dout
+        din = hidden
+    return offs, o
+
+
+def mlp_forward(params, X, n_in, hidden, layers, n_out):
+    p, X = _c64(params), _c64(X)
+    out = np.empty((X.shape[0], n_out))
+    lib().mlp_oracle_forward(_p(p), n_in, _p(X), X.shape[0], hidden, layers, n_out, _p(out), None)
+    return out
+
+
+def mlp_loss_grad(params, X, Y, n_in, hidden, layers, n_out):
+    p, X, Y = _c64(params), _c64(X), _c64(Y)
+    g = np.empty(len(p))
+    loss = lib().mlp_oracle_loss_grad(_p(p), n_in, _p(X), _p(Y), X.shape[0], hidden, layers, n_out, _p(g))
+    return loss, g
+
+
+def mlp_adam(p, g, m, v, t, lr, b1=0.9, b2=0.999, eps=1e-8):
+    """One Adam step in place on float64 arrays p, m, v."""
+    gg = _c64(g)
+    lib().mlp_oracle_adam(_p(p), _p(gg), _p(m), _p(v), len(p), int(t), float(lr), float(b1), float(b2), float(eps))
+
+
+def features(X, y, sub):
+    X, y, sub = _c64(X), _c64(y), _ci64(sub)
+    d = X.shape[1]
+    f = np.empty(4 + 5 * (d + 2))
+    st = lib().sbv_oracle_features(_p(X), _p(y), X.shape[0], d, _p(sub, _i64), len(sub), _p(f))
+    if st:
+        raise ValueError("oracle features rejected its arguments")
+    return f

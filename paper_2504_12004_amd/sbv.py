@@ -23,6 +23,7 @@ _d = C.POINTER(C.c_double)
 _i64 = C.POINTER(C.c_int64)
 _i32 = C.POINTER(C.c_int32)
 _h = C.c_void_p
+_f32 = C.POINTER(C.c_float)
 
 
 class SBVError(RuntimeError):
@@ -76,6 +77,17 @@ def lib():
         "sbv_fit": (C.c_int, [_h, _d, C.c_int32, C.POINTER(sbv_fit_opts), _d, _d, _i32, _d]),
         "sbv_minimize": (C.c_int, [C.c_int32, C.c_int32, _d, C.c_void_p, C.c_void_p, C.POINTER(sbv_fit_opts), _d,
                                    _i32]),
+        "sbv_mlp_create": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_uint64, C.POINTER(_h)]),
+        "sbv_mlp_free": (None, [_h]),
+        "sbv_mlp_num_params": (C.c_int64, [_h]),
+        "sbv_mlp_get_params": (C.c_int, [_h, _f32]),
+        "sbv_mlp_set_params": (C.c_int, [_h, _f32]),
+        "sbv_mlp_loss_grad": (C.c_int, [_h, _f32, _f32, C.c_int32, _f32, _f32]),
+        "sbv_mlp_train": (C.c_int, [_h, _f32, _f32, C.c_int64, C.c_int32, C.c_int32, C.c_float, C.c_uint64, _f32]),
+        "sbv_mlp_predict": (C.c_int, [_h, _f32, C.c_int64, _f32]),
+        "sbv_mlp_save": (C.c_int, [_h, C.c_char_p]),
+        "sbv_mlp_load": (C.c_int, [C.c_char_p, C.POINTER(_h)]),
+        "sbv_features": (C.c_int, [_d, _d, C.c_int64, C.c_int32, C.c_int64, C.c_uint64, _d]),
         "sbv_timing_enable": (C.c_int, [C.c_int32]),
         "sbv_timing_read": (C.c_int, [C.c_int32, _i32, _d, _i64]),
         "sbv_plan_flops": (C.c_int, [C.POINTER(_h), C.c_int32, _i32, _d, _i32, _i32]),
@@ -337,3 +349,97 @@ def sbv_fit(b, theta0, two_nu, opts):
     if st not in (SBV_OK, SBV_E_NOCONV):
         _check(st)
     return out, l64.value, ne.value, sec.value, st == SBV_OK
+
+
+def _cf32(a):
+    return np.ascontiguousarray(a, dtype=np.float32)
+
+
+class MLP:
+    """Owning wrapper of an sbv_mlp handle."""
+
+    def __init__(self, handle, n_out=None):
+        self.handle = C.c_void_p(handle)
+        self.num_params = lib().sbv_mlp_num_params(self.handle)
+        self.n_out = n_out
+
+    def free(self):
+        if self.handle is not None and self.handle.value:
+            lib().sbv_mlp_free(self.handle)
+        self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def sbv_mlp_create(n_in, hidden, layers, n_out, seed=0):
+    h = C.c_void_p()
+    _check(lib().sbv_mlp_create(int(n_in), int(hidden), int(layers), int(n_out), int(seed), C.byref(h)))
+    return MLP(h.value, int(n_out))
+
+
+def sbv_mlp_free(m):
+    m.free()
+
+
+def sbv_mlp_num_params(m):
+    return m.num_params
+
+
+def sbv_mlp_get_params(m):
+    out = np.empty(m.num_params, np.float32)
+    _check(lib().sbv_mlp_get_params(m.handle, _p(out, _f32)))
+    return out
+
+
+def sbv_mlp_set_params(m, params):
+    p = _cf32(params)
+    _check(lib().sbv_mlp_set_params(m.handle, _p(p, _f32)))
+
+
+def sbv_mlp_loss_grad(m, X, Y):
+    X, Y = _cf32(X), _cf32(Y)
+    loss = C.c_float()
+    g = np.empty(m.num_params, np.float32)
+    _check(lib().sbv_mlp_loss_grad(m.handle, _p(X, _f32), _p(Y, _f32), X.shape[0], C.byref(loss), _p(g, _f32)))
+    return loss.value, g
+
+
+def sbv_mlp_train(m, X, Y, epochs, batch=256, lr=1e-3, seed=0):
+    X, Y = _cf32(X), _cf32(Y)
+    fl = C.c_float()
+    _check(lib().sbv_mlp_train(m.handle, _p(X, _f32), _p(Y, _f32), X.shape[0], int(epochs), int(batch), float(lr),
+                               int(seed), C.byref(fl)))
+    return fl.value
+
+
+def sbv_mlp_predict(m, X):
+    X = _cf32(X)
+    out = np.empty((X.shape[0], _mlp_out(m)), np.float32)
+    _check(lib().sbv_mlp_predict(m.handle, _p(X, _f32), X.shape[0], _p(out, _f32)))
+    return out
+
+
+def _mlp_out(m):
+    return m.n_out
+
+
+def sbv_mlp_save(m, path):
+    _check(lib().sbv_mlp_save(m.handle, str(path).encode()))
+
+
+def sbv_mlp_load(path, n_out):
+    h = C.c_void_p()
+    _check(lib().sbv_mlp_load(str(path).encode(), C.byref(h)))
+    return MLP(h.value, int(n_out))
+
+
+def sbv_features(X, y, sub_n=20000, seed=0):
+    X, y = _c64(X), _c64(y)
+    n, d = X.shape
+    f = np.empty(4 + 5 * (d + 2))
+    _check(lib().sbv_features(_p(X), _p(y), n, d, int(sub_n), int(seed), _p(f)))
+    return f
