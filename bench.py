@@ -43,7 +43,22 @@ def main():
     ap.add_argument("--n", type=int, default=None, help="override n (testing only)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy (to scale HBM byte counters)")
+    ap.add_argument("--fit-evals", type=int, default=300,
+                    help="evaluation budget of each MLE fit leg (0 skips the fits)")
+    ap.add_argument("--traffic-json", default=None,
+                    help="JSON with measured per-launch HBM bytes of the dominant kernel")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda:0")  # 1 GiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": src.numel() * 8, "launches": 3}))
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
                           "n_gpus": args.gpus}))
@@ -141,6 +156,10 @@ def main():
     except sbv.SBVError:
         pass
 
+    fits = None
+    if args.fit_evals > 0:
+        fits = fit_legs(B, sbv, theta_true, two_nu, w, args.fit_evals)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(B, X, sbv, theta_true, two_nu, args.cpu_seconds)
@@ -161,7 +180,7 @@ def main():
         "config": {"workload": "uneven_1m: n=1e6 d=10 Matern-5/2 tau2=1e-4 kmeans K=5e4 (5..60) m=200",
                    "n": n, "d": d, "blocks": B.K, "m": m, "parallelism": "1 GPU"},
         "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK_FP64 / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64, "traffic": traffic(args.traffic_json),
                      "kernel": f"k_block_loglik<double,{tiles[v_dom]}>",
                      "flop_per_launch": flops[v_dom], "avg_launch_ms": avg_ms},
         "extra": {
@@ -171,11 +190,47 @@ def main():
             "fp32_fallback_blocks": int(fb),
             "grad_fp64_evals_per_s": grad_rate,
             "build_seconds": t_build,
+            "fits": fits,
         },
     }
     if cpu is not None:
         res["cpu_baseline"] = cpu
     print(json.dumps(res), flush=True)
+
+
+def fit_legs(B, sbv, theta_true, two_nu, w, max_evals):
+    """MLE wall time on the resident structure from the cold start
+    (beta_k = 1, sigma^2 = var(y), tau^2 = 1e-3 var(y)): plain FP64
+    Nelder-Mead versus FP32 L-BFGS with an FP64 polish; each leg's optimum is
+    judged by one FP64 evaluation."""
+    d = w["d"]
+    var_y = 1.0
+    x0 = np.r_[np.zeros(d), np.log(var_y), np.log(1e-3 * var_y)]
+    out = {}
+    legs = [("nelder_mead_fp64", sbv.SBV_NELDER_MEAD, sbv.SBV_FP64, False),
+            ("lbfgs_fp32_polish64", sbv.SBV_LBFGS, sbv.SBV_FP32, True),
+            ("lbfgs_fp64", sbv.SBV_LBFGS, sbv.SBV_FP64, False)]
+    for name, opt, prec, polish in legs:
+        o = sbv.make_fit_opts(optimizer=opt, prec=prec, fp64_polish=polish, max_evals=max_evals, ftol=1e-10,
+                              gtol=1e-3, init_step=0.5)
+        th, l64, ne, sec, conv = sbv.sbv_fit(B, x0, two_nu, o)
+        out[name] = {"seconds": sec, "evals": ne, "loglik_fp64": l64, "converged": conv}
+        log(f"fit {name}: {sec:.2f}s, {ne} evals, l64 {l64:.6f}, converged {conv}")
+    base = out["nelder_mead_fp64"]["loglik_fp64"]
+    for k in out:
+        out[k]["rel_gap_vs_nm64"] = (out[k]["loglik_fp64"] - base) / abs(base)
+    return out
+
+
+def traffic(path):
+    """Per-launch HBM bytes of the dominant kernel from a counter summary
+    (FETCH_SIZE + WRITE_SIZE, each scaled by the plain-copy calibration), or
+    None when no summary for the current kernel is given."""
+    if not path or not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    return t.get("bytes_per_launch")
 
 
 def cpu_baseline(B, X, sbv, theta, two_nu, seconds):

@@ -229,6 +229,31 @@ sbv_status sbv_mlp_load(const char* path, sbv_mlp* h);
 sbv_status sbv_features(const double* X, const double* y, int64_t n, int32_t d, int64_t sub_n, uint64_t seed,
                         double* feat);
 
+/*
+ * Batched evaluation of many datasets as one captured launch sequence.  The
+ * first call for a (sets, two_nu, prec, with_grad) combination captures every
+ * kernel of the evaluation -- all size buckets of all sets, the FP32 fallback
+ * pass, the reductions -- into a hipGraph; later calls replay it.  theta_dev
+ * (packed per set) is copied into the plan's fixed parameter buffer before the
+ * replay and loglik_dev (n_sets) / grad_dev (packed per set, with_grad only)
+ * are copied out after it, all on `stream`.
+ */
+sbv_status sbv_eval_graph_dev(const sbv_blocks* sets, int32_t n_sets, const double* theta_dev,
+                              const int32_t* two_nu, int32_t prec, int32_t with_grad, double* loglik_dev,
+                              double* grad_dev, void* stream);
+
+/*
+ * Autotuner: for every size bucket of the sets' plan, time `reps` launches of
+ * each kernel variant able to hold the bucket's joint sizes, with and without
+ * the lookahead schedule (the next diagonal tile factored during the current
+ * trailing update), at theta (host, packed per set) and precision prec, and
+ * keep the fastest for later evaluations.
+ * chosen_tiles (optional, 16 entries) receives the chosen tile capacity per
+ * bucket, longest bucket first.  Synchronous.
+ */
+sbv_status sbv_autotune(const sbv_blocks* sets, int32_t n_sets, const int32_t* two_nu, const double* theta,
+                        int32_t prec, int32_t reps, int32_t* chosen_tiles);
+
 /* Number of blocks recomputed in FP64 by the last SBV_FP32 evaluation of this
  * handle (synchronises the device). */
 sbv_status sbv_blocks_fallback_count(sbv_blocks h, int64_t* count);

@@ -12,6 +12,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -111,7 +112,10 @@ struct sbv_blocks_s {
 
 // ---- evaluation plans ------------------------------------------------------
 struct Bucket {
-  int variant = -1;
+  int variant = -1;        // smallest variant holding the bucket's joint sizes
+  int tuned[2] = {-1, -1};  // autotuned variant per precision (-1: use `variant`)
+  bool la[2] = {false, false};  // lookahead schedule per precision (autotuned)
+  int use(int prec) const { return tuned[prec] >= 0 ? tuned[prec] : variant; }
   int count = 0;           // host copy of the item count
   DevBuf<WorkItem> items;  // sorted by joint size, longest first
   DevBuf<int> dcount;      // device copy of count
@@ -121,6 +125,15 @@ struct Bucket {
 
 struct Plan {
   std::vector<sbv_blocks> sets;
+  // captured evaluations: index = 2 * grad + prec
+  hipGraph_t graph[4] = {nullptr, nullptr, nullptr, nullptr};
+  hipGraphExec_t exec[4] = {nullptr, nullptr, nullptr, nullptr};
+  ~Plan() {
+    for (int i = 0; i < 4; ++i) {
+      if (exec[i]) (void)hipGraphExecDestroy(exec[i]);
+      if (graph[i]) (void)hipGraphDestroy(graph[i]);
+    }
+  }
   std::vector<SetDesc> hdesc;      // host copy of the set descriptors
   std::vector<DevBuf<double>> qbuf;  // adjoint buffers (allocated on the first gradient call)
   std::vector<DevBuf<int64_t>> qoff;
@@ -228,6 +241,10 @@ sbv_status get_plan(const sbv_blocks* sets, int32_t n_sets, const int32_t* two_n
     HIP_TRY(hipMemcpy(B.dcount.p, &B.count, sizeof(int), hipMemcpyHostToDevice));
     HIP_TRY(B.fb_items.alloc(it.size()));
     HIP_TRY(B.fb_count.alloc(1));
+    // SBV_LOOKAHEAD=1 selects the lookahead schedule for new plans (the
+    // autotuner may change it per bucket later)
+    const char* la = std::getenv("SBV_LOOKAHEAD");
+    B.la[0] = B.la[1] = la && la[0] == '1';
     P->buckets.push_back(std::move(B));
   }
   *out = P.get();
@@ -302,14 +319,15 @@ sbv_status run_plan_grad(Plan* P, int32_t prec, hipStream_t s) {
 // result in P->out.
 sbv_status run_plan(Plan* P, int32_t prec, hipStream_t s) {
   for (auto& B : P->buckets) {
-    TimedLaunch tl{prec == SBV_FP32 ? 1 : 0, B.variant, nullptr, nullptr};
+    TimedLaunch tl{prec == SBV_FP32 ? 1 : 0, B.use(prec == SBV_FP32 ? 1 : 0), nullptr, nullptr};
     if (g_timing) {
       HIP_TRY(hipEventCreate(&tl.a));
       HIP_TRY(hipEventCreate(&tl.b));
       HIP_TRY(hipEventRecord(tl.a, s));
     }
-    HIP_TRY(launch_loglik(prec == SBV_FP32 ? 1 : 0, B.variant, B.count, P->dsets.p, P->theta.p,
-                          B.items.p, B.dcount.p, prec == SBV_FP32 ? g_piv_tau : 0.0, s));
+    const int pk = prec == SBV_FP32 ? 1 : 0;
+    HIP_TRY(launch_loglik(pk, B.use(pk), B.count, P->dsets.p, P->theta.p, B.items.p, B.dcount.p,
+                          pk ? g_piv_tau : 0.0, s, false, B.la[pk]));
     if (g_timing) {
       HIP_TRY(hipEventRecord(tl.b, s));
       g_timed.push_back(tl);
@@ -317,9 +335,8 @@ sbv_status run_plan(Plan* P, int32_t prec, hipStream_t s) {
     if (prec == SBV_FP32) {
       HIP_TRY(launch_zero_int(B.fb_count.p, 1, s));
       HIP_TRY(launch_flag_compact(P->dsets.p, B.items.p, B.dcount.p, B.fb_items.p, B.fb_count.p, s));
-      int grid = std::min(B.count, max_grid(0, B.variant));
-      HIP_TRY(launch_loglik(0, B.variant, grid, P->dsets.p, P->theta.p, B.fb_items.p, B.fb_count.p,
-                            0.0, s));
+      int grid = std::min(B.count, max_grid(0, B.use(0)));
+      HIP_TRY(launch_loglik(0, B.use(0), grid, P->dsets.p, P->theta.p, B.fb_items.p, B.fb_count.p, 0.0, s));
     }
   }
   HIP_TRY(launch_reduce(P->dsets.p, (int)P->sets.size(), nullptr, P->out.p, P->bad.p, s));
@@ -606,6 +623,105 @@ sbv_status sbv_sample(sbv_blocks h, const double* theta, int32_t two_nu, const d
   if (st) return st;
   if (y) HIP_TRY(hipMemcpy(y, yy.p, sizeof(double) * h->n, hipMemcpyDeviceToHost));
   HIP_TRY(hipDeviceSynchronize());
+  return SBV_OK;
+}
+
+// ---- autotuner: per size bucket, time every kernel variant that can hold the
+// bucket's largest joint size and keep the fastest.
+sbv_status sbv_autotune(const sbv_blocks* sets, int32_t n_sets, const int32_t* two_nu, const double* theta,
+                        int32_t prec, int32_t reps, int32_t* chosen_tiles) {
+  sbv_status st = check_sets(sets, n_sets, two_nu);
+  if (st) return st;
+  if (!theta || reps <= 0) return fail(SBV_E_INVAL, "theta and reps > 0 are required");
+  Plan* P = nullptr;
+  st = get_plan(sets, n_sets, two_nu, &P);
+  if (st) return st;
+  HIP_TRY(hipMemcpy(P->theta.p, theta, sizeof(double) * P->theta_len, hipMemcpyHostToDevice));
+  const int pk = prec == SBV_FP32 ? 1 : 0;
+  hipEvent_t a, b;
+  HIP_TRY(hipEventCreate(&a));
+  HIP_TRY(hipEventCreate(&b));
+  int bi = 0;
+  for (auto& B : P->buckets) {
+    // the bucket's own variant is the smallest that fits; candidates are it and all larger ones
+    const int base = B.variant;
+    float best = INFINITY;
+    int bestv = base;
+    bool bestla = false;
+    for (int v = base; v < n_variants(); ++v)
+      for (int la = 0; la < 2; ++la) {
+        HIP_TRY(launch_loglik(pk, v, B.count, P->dsets.p, P->theta.p, B.items.p, B.dcount.p, 0.0, nullptr, false,
+                              la != 0));
+        HIP_TRY(hipEventRecord(a, nullptr));
+        for (int r = 0; r < reps; ++r)
+          HIP_TRY(launch_loglik(pk, v, B.count, P->dsets.p, P->theta.p, B.items.p, B.dcount.p, 0.0, nullptr,
+                                false, la != 0));
+        HIP_TRY(hipEventRecord(b, nullptr));
+        HIP_TRY(hipEventSynchronize(b));
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, a, b));
+        if (ms < best) {
+          best = ms;
+          bestv = v;
+          bestla = la != 0;
+        }
+      }
+    B.tuned[pk] = bestv;
+    B.la[pk] = bestla;
+    if (chosen_tiles) chosen_tiles[bi] = variant(bestv).ntm;
+    ++bi;
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  // captured graphs may hold the old choice
+  for (int i = 0; i < 4; ++i) {
+    if (P->exec[i]) (void)hipGraphExecDestroy(P->exec[i]);
+    if (P->graph[i]) (void)hipGraphDestroy(P->graph[i]);
+    P->exec[i] = nullptr;
+    P->graph[i] = nullptr;
+  }
+  return SBV_OK;
+}
+
+// ---- graph-captured evaluation of a whole plan ------------------------------
+// The kernels of one evaluation (every bucket of every set, the FP32 fallback
+// pass and the reductions) are captured once into a hipGraph; theta enters
+// through the plan's fixed device buffer and results leave through the plan's
+// output buffers, so the graph's parameters never change.
+sbv_status sbv_eval_graph_dev(const sbv_blocks* sets, int32_t n_sets, const double* theta_dev,
+                              const int32_t* two_nu, int32_t prec, int32_t with_grad, double* loglik_dev,
+                              double* grad_dev, void* stream) {
+  sbv_status st = check_sets(sets, n_sets, two_nu);
+  if (st) return st;
+  if (!theta_dev || !loglik_dev || (with_grad && !grad_dev)) return fail(SBV_E_INVAL, "device buffers required");
+  if (prec != SBV_FP64 && prec != SBV_FP32) return fail(SBV_E_INVAL, "prec must be SBV_FP64 or SBV_FP32");
+  Plan* P = nullptr;
+  st = get_plan(sets, n_sets, two_nu, &P);
+  if (st) return st;
+  if (with_grad) {
+    st = ensure_adjoint(P);
+    if (st) return st;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  const int gi = 2 * (with_grad ? 1 : 0) + (prec == SBV_FP32 ? 1 : 0);
+  if (!P->exec[gi]) {
+    hipStream_t cs;
+    HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    sbv_status rs = with_grad ? run_plan_grad(P, prec, cs) : run_plan(P, prec, cs);
+    hipGraph_t g = nullptr;
+    hipError_t ce = hipStreamEndCapture(cs, &g);
+    (void)hipStreamDestroy(cs);
+    if (rs) return rs;
+    if (ce != hipSuccess) return fail(SBV_E_DEVICE, std::string("graph capture failed: ") + hipGetErrorString(ce));
+    P->graph[gi] = g;
+    HIP_TRY(hipGraphInstantiate(&P->exec[gi], g, nullptr, nullptr, 0));
+  }
+  HIP_TRY(hipMemcpyAsync(P->theta.p, theta_dev, sizeof(double) * P->theta_len, hipMemcpyDeviceToDevice, s));
+  HIP_TRY(hipGraphLaunch(P->exec[gi], s));
+  HIP_TRY(hipMemcpyAsync(loglik_dev, P->out.p, sizeof(double) * n_sets, hipMemcpyDeviceToDevice, s));
+  if (with_grad)
+    HIP_TRY(hipMemcpyAsync(grad_dev, P->grad.p, sizeof(double) * P->theta_len, hipMemcpyDeviceToDevice, s));
   return SBV_OK;
 }
 

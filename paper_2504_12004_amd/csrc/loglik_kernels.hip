@@ -114,6 +114,7 @@ struct Smem {
   T zk[kTile];                 // solved z of the current tile row
   T zfull[GRAD ? NTM * kTile : 1];  // all of z = L^{-1} y (GRAD only)
   T xi[NTM * kTile];                // innovations of the conditional simulator
+  int la_flag;                      // lookahead: last diagonal step published
   T gv[GRAD ? NTM * kTile : 1];     // g = Q z_B accumulated over chunks (GRAD only)
 };
 
@@ -276,6 +277,135 @@ __device__ __forceinline__ void refresh_slots(int* ti, int* tj) {
     asm volatile("" : "+v"(a), "+v"(b));
     ti[s] = __builtin_amdgcn_readfirstlane(a);
     tj[s] = __builtin_amdgcn_readfirstlane(b);
+  }
+}
+
+// ---- lookahead schedule (forward log-likelihood only) ----------------------
+// The owner of the next diagonal tile updates it first in the trailing update
+// of step k and publishes it with an LDS flag; the panel wave factors it while
+// the workers finish step k.  Two barriers per step instead of three.
+template <typename T, int NTM, int NTHR, class SM>
+__device__ void panel_wave_la(SM& sm, int lane, int nt, int mi, int nA, int d, int two_nu, T sigma2, T tau2, T tau,
+                              double& ld_acc, double& q_acc, int& bad, int& low) {
+  const T diag0 = sigma2 + tau2;
+  for (int j = 0; j < nt; ++j) {
+    gen_column<T, NTHR>(sm, lane, j, nt, nA, d, two_nu, sigma2, tau2);
+    __syncthreads();  // G1
+    __syncthreads();  // G2
+  }
+  auto factor_step = [&](int k) {
+    while (__atomic_load_n(&sm.la_flag, __ATOMIC_ACQUIRE) < k) __builtin_amdgcn_s_sleep(1);
+    T piv, zr;
+    factor_diag<T>(sm, lane, k, nA - kTile * k, diag0, tau, piv, zr, bad, low);
+    const int rowg = kTile * k + lane;
+    if (lane < 16) {
+      sm.zk[lane] = zr;
+      if (rowg >= mi && rowg < nA) {
+        ld_acc += log((double)piv);
+        q_acc += (double)zr * (double)zr;
+      }
+    }
+  };
+  factor_step(0);
+  __syncthreads();  // P0: step 0 factored
+  for (int k = 0; k < nt; ++k) {
+    __syncthreads();  // S3: column k of L published
+    for (int rho = kTile * (k + 1) + lane; rho < kTile * nt; rho += 64) {
+      const T* P = sm.panel + 256 * (rho >> 4);
+      const int rr = rho & 15;
+      T v = sm.yv[rho];
+#pragma unroll
+      for (int c = 0; c < 16; ++c) v -= P[opoff<T>(rr, c)] * sm.zk[c];
+      sm.yv[rho] = v;
+    }
+    if (k + 1 < nt) factor_step(k + 1);
+    __syncthreads();  // S4: trailing update and next diagonal done
+  }
+}
+
+template <typename T, int NTM, int NWK, int NTHR, class SM>
+__device__ void worker_waves_la(SM& sm, int wk, int lane, int nt, int nA, int d, int two_nu, T sigma2, T tau2) {
+  typedef typename MF<T>::acc acc_t;
+  constexpr int NTT = NTM * (NTM + 1) / 2;
+  constexpr int SLOTS = (NTT + NWK - 1) / NWK;
+  const int g = lane >> 4;
+  const int cl = lane & 15;
+  const int ntt = nt * (nt + 1) / 2;
+  int ti[SLOTS], tj[SLOTS];
+#pragma unroll
+  for (int s = 0; s < SLOTS; ++s) {
+    int t = s * NWK + wk;
+    int i = -1, j = -1;
+    if (t < ntt) {
+      j = 0;
+      while (t >= nt - j) {
+        t -= nt - j;
+        ++j;
+      }
+      i = j + t;
+    }
+    ti[s] = __builtin_amdgcn_readfirstlane(i);
+    tj[s] = __builtin_amdgcn_readfirstlane(j);
+  }
+  acc_t acc[SLOTS];
+#pragma unroll
+  for (int s = 0; s < SLOTS; ++s) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc[s][t] = T(0);
+  }
+  for (int j = 0; j < nt; ++j) {
+    refresh_slots<SLOTS>(ti, tj);
+    gen_column<T, NTHR>(sm, 64 * (wk + 1) + lane, j, nt, nA, d, two_nu, sigma2, tau2);
+    __syncthreads();  // G1
+#pragma unroll
+    for (int s = 0; s < SLOTS; ++s) {
+      if (tj[s] == j) {
+        const T* src = sm.panel + 256 * ti[s];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) acc[s][t] = src[64 * t + lane];
+      }
+    }
+    __syncthreads();  // G2
+  }
+  auto publish_diag = [&](int s, int k) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) sm.diag[cl * 16 + MF<T>::row(g, t)] = -acc[s][t];
+    __builtin_amdgcn_s_waitcnt(0);
+    __builtin_amdgcn_wave_barrier();
+    if (lane == 0) __atomic_store_n(&sm.la_flag, k, __ATOMIC_RELEASE);
+  };
+#pragma unroll
+  for (int s = 0; s < SLOTS; ++s)
+    if (ti[s] == 0 && tj[s] == 0) publish_diag(s, 0);
+  __syncthreads();  // P0
+  for (int k = 0; k < nt; ++k) {
+    refresh_slots<SLOTS>(ti, tj);
+#pragma unroll
+    for (int s = 0; s < SLOTS; ++s) {
+      if (tj[s] == k && ti[s] > k) {
+        acc_t o = {T(0), T(0), T(0), T(0)};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) o = MF<T>::mma(acc[s][q], sm.negM[64 * q + lane], o);
+        acc[s] = o;
+        T* P = sm.panel + 256 * ti[s];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) P[opoff<T>(MF<T>::row(g, t), cl)] = o[t];
+      }
+    }
+    __syncthreads();  // S3
+#pragma unroll
+    for (int s = 0; s < SLOTS; ++s) {
+      if (tj[s] > k) {
+        const T* Pj = sm.panel + 256 * tj[s];
+        const T* Pi = sm.panel + 256 * ti[s];
+        acc_t o = acc[s];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) o = MF<T>::mma(Pj[64 * q + lane], Pi[64 * q + lane], o);
+        acc[s] = o;
+        if (ti[s] == k + 1 && tj[s] == k + 1) publish_diag(s, k + 1);
+      }
+    }
+    __syncthreads();  // S4
   }
 }
 
@@ -482,7 +612,7 @@ __device__ void panel_adjoint(SM& sm, int lane, int nt, int mi, int nA, int bi, 
   for (int r = lane; r < nA; r += NTHR) gout[nA + r] = sm.gv[r];
 }
 
-template <typename T, int NTM, int NW, bool GRAD, bool SAMPLE = false>
+template <typename T, int NTM, int NW, bool GRAD, bool SAMPLE = false, bool LA = false>
 __global__ __launch_bounds__(NW * 64) void k_block_loglik(const SetDesc* __restrict__ sets,
                                                           const double* __restrict__ theta,
                                                           const WorkItem* __restrict__ items,
@@ -519,13 +649,18 @@ __global__ __launch_bounds__(NW * 64) void k_block_loglik(const SetDesc* __restr
       sm.yv[p] = v;
       if (SAMPLE) sm.xi[p] = (p >= mi && p < nA) ? T(S.xi[b0 + (p - mi)]) : T(0);
     }
+    if (tid == 0) sm.la_flag = -1;
     __syncthreads();
 
     if (wave == 0) {
       double ld_acc = 0.0, q_acc = 0.0;
       int bad = 0, low = 0;
-      panel_wave<T, NTM, NW * 64, GRAD, SAMPLE>(sm, lane, nt, mi, nA, d, S.two_nu, sigma2, tau2, T(piv_tau),
-                                                ld_acc, q_acc, bad, low, S.y_out + b0);
+      if (LA)
+        panel_wave_la<T, NTM, NW * 64>(sm, lane, nt, mi, nA, d, S.two_nu, sigma2, tau2, T(piv_tau), ld_acc, q_acc,
+                                       bad, low);
+      else
+        panel_wave<T, NTM, NW * 64, GRAD, SAMPLE>(sm, lane, nt, mi, nA, d, S.two_nu, sigma2, tau2, T(piv_tau),
+                                                  ld_acc, q_acc, bad, low, S.y_out + b0);
 #pragma unroll
       for (int off = 8; off >= 1; off >>= 1) {
         ld_acc += __shfl_xor(ld_acc, off, 16);
@@ -540,8 +675,11 @@ __global__ __launch_bounds__(NW * 64) void k_block_loglik(const SetDesc* __restr
       }
       if (GRAD) panel_adjoint<T, NW * 64>(sm, lane, nt, mi, nA, bi, gout);
     } else {
-      worker_waves<T, NTM, NW - 1, NW * 64, GRAD>(sm, wave - 1, lane, nt, mi, nA, bi, d, S.two_nu, sigma2, tau2,
-                                                  gout);
+      if (LA)
+        worker_waves_la<T, NTM, NW - 1, NW * 64>(sm, wave - 1, lane, nt, nA, d, S.two_nu, sigma2, tau2);
+      else
+        worker_waves<T, NTM, NW - 1, NW * 64, GRAD>(sm, wave - 1, lane, nt, mi, nA, bi, d, S.two_nu, sigma2, tau2,
+                                                    gout);
     }
     __syncthreads();
   }
@@ -715,9 +853,12 @@ int variant_for(int nA) {
 }
 
 template <typename T, int NTM, int NW>
-static hipError_t launch_t(int grid, bool grad, const SetDesc* sets, const double* theta, const WorkItem* items,
-                           const int* count, double piv_tau, hipStream_t s) {
-  if (grad)
+static hipError_t launch_t(int grid, bool grad, bool la, const SetDesc* sets, const double* theta,
+                           const WorkItem* items, const int* count, double piv_tau, hipStream_t s) {
+  if (la && !grad)
+    hipLaunchKernelGGL((k_block_loglik<T, NTM, NW, false, false, true>), dim3(grid), dim3(NW * 64), 0, s, sets,
+                       theta, items, count, piv_tau);
+  else if (grad)
     hipLaunchKernelGGL((k_block_loglik<T, NTM, NW, true>), dim3(grid), dim3(NW * 64), 0, s, sets, theta, items,
                        count, piv_tau);
   else
@@ -752,9 +893,10 @@ static hipError_t launch_c(int grid, const SetDesc* sets, const double* theta, c
   }
 
 hipError_t launch_loglik(int prec, int v, int grid, const SetDesc* sets, const double* theta,
-                         const WorkItem* items, const int* count, double piv_tau, hipStream_t s, bool grad) {
+                         const WorkItem* items, const int* count, double piv_tau, hipStream_t s, bool grad,
+                         bool lookahead) {
   if (grid <= 0) return hipSuccess;
-#define SBV_CALL(T, A, B) launch_t<T, A, B>(grid, grad, sets, theta, items, count, piv_tau, s)
+#define SBV_CALL(T, A, B) launch_t<T, A, B>(grid, grad, lookahead, sets, theta, items, count, piv_tau, s)
   if (prec == 0) {
     SBV_VARIANT_SWITCH(double, SBV_CALL)
   } else {

@@ -49,7 +49,7 @@ struct Variant {
 // items[blockIdx.x + k*gridDim.x] while the index is below *count.
 hipError_t launch_loglik(int prec, int variant, int grid, const SetDesc* sets, const double* theta,
                          const WorkItem* items, const int* count, double piv_tau, hipStream_t s,
-                         bool grad = false);
+                         bool grad = false, bool lookahead = false);
 hipError_t launch_contract(int prec, int variant, int grid, const SetDesc* sets, const double* theta,
                            const WorkItem* items, const int* count, hipStream_t s);
 hipError_t launch_sample(int variant, int grid, const SetDesc* sets, const double* theta,

@@ -88,6 +88,9 @@ def lib():
         "sbv_mlp_save": (C.c_int, [_h, C.c_char_p]),
         "sbv_mlp_load": (C.c_int, [C.c_char_p, C.POINTER(_h)]),
         "sbv_features": (C.c_int, [_d, _d, C.c_int64, C.c_int32, C.c_int64, C.c_uint64, _d]),
+        "sbv_eval_graph_dev": (C.c_int, [C.POINTER(_h), C.c_int32, C.c_void_p, _i32, C.c_int32, C.c_int32,
+                                         C.c_void_p, C.c_void_p, C.c_void_p]),
+        "sbv_autotune": (C.c_int, [C.POINTER(_h), C.c_int32, _i32, _d, C.c_int32, C.c_int32, _i32]),
         "sbv_timing_enable": (C.c_int, [C.c_int32]),
         "sbv_timing_read": (C.c_int, [C.c_int32, _i32, _d, _i64]),
         "sbv_plan_flops": (C.c_int, [C.POINTER(_h), C.c_int32, _i32, _d, _i32, _i32]),
@@ -443,3 +446,21 @@ def sbv_features(X, y, sub_n=20000, seed=0):
     f = np.empty(4 + 5 * (d + 2))
     _check(lib().sbv_features(_p(X), _p(y), n, d, int(sub_n), int(seed), _p(f)))
     return f
+
+
+def sbv_eval_graph_dev(sets, theta_dev, two_nu, out_dev, prec=SBV_FP64, grad_dev=None, stream=None):
+    hs, ns = _handles(sets)
+    tn = np.ascontiguousarray(np.broadcast_to(np.asarray(two_nu, np.int32), (ns,)), dtype=np.int32)
+    _check(lib().sbv_eval_graph_dev(hs, ns, C.c_void_p(_ptr(theta_dev)), _p(tn, _i32), int(prec),
+                                    int(grad_dev is not None), C.c_void_p(_ptr(out_dev)),
+                                    C.c_void_p(_ptr(grad_dev) if grad_dev is not None else 0),
+                                    C.c_void_p(_stream(stream))))
+
+
+def sbv_autotune(sets, theta, two_nu, prec=SBV_FP64, reps=2):
+    hs, ns = _handles(sets)
+    th = _c64(np.concatenate([np.ravel(t) for t in theta]) if isinstance(theta, (list, tuple)) else theta)
+    tn = np.ascontiguousarray(np.broadcast_to(np.asarray(two_nu, np.int32), (ns,)), dtype=np.int32)
+    ch = np.zeros(16, np.int32)
+    _check(lib().sbv_autotune(hs, ns, _p(tn, _i32), _p(th), int(prec), int(reps), _p(ch, _i32)))
+    return ch[ch > 0]

@@ -92,3 +92,10 @@ def test_sampler_matches_oracle(sbv):
     # the handle now holds the draw: its log-likelihood matches the oracle's on it
     got = sbv.sbv_loglik(B, th, 5)[0]
     assert abs(got - O.sbv_loglik(X, ref, S, th, 5)) <= 1e-10 * abs(got)
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-10), (1, 1e-4)])
+def test_lookahead_schedule_matches_oracle(sbv, prec, tol, monkeypatch):
+    monkeypatch.setenv("SBV_LOOKAHEAD", "1")
+    X, y, th, S = problem(6000, 10, K=300, m=230, seed=27, tau2=1e-4, max_bs=30)
+    _check(sbv, X, y, th, S, 5, prec, tol)
