@@ -262,9 +262,17 @@ struct TimedLaunch {
 bool g_timing = false;
 std::vector<TimedLaunch> g_timed;
 
-// Piv threshold of the FP32 path: a block whose FP32 pivot falls to or below
-// this fraction of the original diagonal is recomputed in FP64.
-double g_piv_tau = 1e-3;
+// Pivot threshold of the FP32 path: a block whose FP32 pivot falls to or below
+// this fraction of the original diagonal is recomputed in FP64.  The
+// environment variable SBV_PIV_TAU overrides it (read once).
+double piv_tau() {
+  static double t = [] {
+    const char* e = std::getenv("SBV_PIV_TAU");
+    return e ? std::atof(e) : 1e-4;
+  }();
+  return t;
+}
+#define g_piv_tau piv_tau()
 
 // Allocate the per-block adjoint buffers (e, g, Q: nA_i (b_i + 2) values per
 // block) of every set of a plan, once.

@@ -95,6 +95,25 @@ __device__ __forceinline__ T matern(T r, int two_nu) {
 
 constexpr double kLog2Pi = 1.83787706640934548356065947281123527;
 
+// Phase profile (profiling builds only, -DSBV_PHASE_PROFILE): cycles spent by
+// the panel wave (slots 0..7) and the first worker wave (slots 8..15) per
+// phase, summed over blocks.
+#ifdef SBV_PHASE_PROFILE
+__device__ unsigned long long g_phase[16];
+#define SBV_PROF_DECL long long prof_t = clock64();
+#define SBV_PROF(slot, cond)                                                        \
+  do {                                                                              \
+    long long now_ = clock64();                                                     \
+    if ((cond) && (threadIdx.x & 63) == 0) atomicAdd(&g_phase[slot], (unsigned long long)(now_ - prof_t)); \
+    prof_t = now_;                                                                  \
+  } while (0)
+#else
+#define SBV_PROF_DECL
+#define SBV_PROF(slot, cond) \
+  do {                       \
+  } while (0)
+#endif
+
 // Row stride of the right-hand-side chunk used by the adjoint solves (32
 // columns plus one of padding so that rows fall on different LDS banks).
 constexpr int kRS = 33;
@@ -118,109 +137,171 @@ struct Smem {
   T gv[GRAD ? NTM * kTile : 1];     // g = Q z_B accumulated over chunks (GRAD only)
 };
 
-// Factor the 16x16 SPD tile in sm.diag on one wave (rows in lanes 0..15,
-// lanes 16..63 shadow them): L by right-looking pivots with readlane
-// broadcasts, the forward solve z_k = L_kk^{-1} y_k folded into the same pivot
-// loop, then X = L^{-1} column by column, published as -X^T.  Lane r < 16
-// returns its pivot L_rr and z_r; `bad` is raised for a non-positive or
-// non-finite pivot and `low` for a pivot at or below tau * original diagonal
-// (the FP32 fallback test).
+// 1/sqrt(p): hardware reciprocal square root refined by Newton steps
+// r <- r (3 - p r^2) / 2 (two for FP64, one for FP32).
+__device__ __forceinline__ double rsqrt_nr(double p) {
+  double r = __builtin_amdgcn_rsq(p);
+  r = r * (1.5 - 0.5 * p * r * r);
+  r = r * (1.5 - 0.5 * p * r * r);
+  return r;
+}
+__device__ __forceinline__ float rsqrt_nr(float p) {
+  float r = __builtin_amdgcn_rsqf(p);
+  return r * (1.5f - 0.5f * p * r * r);
+}
+
+__device__ __forceinline__ double shfl_d(double v, int src) { return __shfl(v, src, 64); }
+__device__ __forceinline__ float shfl_d(float v, int src) { return __shfl(v, src, 64); }
+
+// Factor the 16x16 SPD tile in sm.diag on one wave with all 64 lanes: lane
+// (r, g) = (l % 16, l / 16) holds columns c = g + 4q (q = 0..3) of row r.
+// Right-looking pivots; by symmetry of the trailing matrix the column-j
+// entries L[c][j] a lane needs are row j's entries of its own columns, read
+// from lane (j, g).  The same loop eliminates the rows of X = L^{-1} (lane
+// (r, g) holds X[r][g + 4q], starting from the identity) and solves
+// z_k = L_kk^{-1} y_k, so no second pass is needed; -X^T is then published
+// for the column solves.  Lanes r < 16 return the pivot L_rr and z_r; `bad`
+// is raised for a non-positive or non-finite pivot and `low` for a pivot at or
+// below tau * original diagonal (the FP32 fallback test).
 template <typename T, bool SAMPLE = false, class SM>
 __device__ void factor_diag(SM& sm, int lane, int k, int nreal, T diag0, T tau, T& pivot_out,
                             T& z_out, int& bad, int& low, int mi = 0, T* ysim = nullptr) {
-  const int r = lane & 15;
-  T a[16];
+  const int r = lane & 15, g = lane >> 4;
+  T a[4], x[4];
 #pragma unroll
-  for (int c = 0; c < 16; ++c) a[c] = sm.diag[r * 16 + c];
+  for (int q = 0; q < 4; ++q) {
+    const int c = g + 4 * q;
+    a[q] = sm.diag[r * 16 + c];
+    x[q] = (c == r) ? T(1) : T(0);
+  }
   T yr = sm.yv[kTile * k + r];
-  T invd[16];
 #pragma unroll
   for (int j = 0; j < 16; ++j) {
-    T piv = rlane(a[j], j);
+    const int gj = j & 3, qj = j >> 2;
+    const T piv = rlane(a[qj], j + 16 * gj);
     if (!(piv > T(0)) || !(piv == piv) || piv > T(3.0e38)) bad = 1;
     if (piv <= tau * (j < nreal ? diag0 : T(1))) low = 1;
-    T sq = t_sqrt(piv);
-    T inv = T(1) / sq;
-    invd[j] = inv;
-    a[j] = (r == j) ? sq : a[j] * inv;
+    const T rs = rsqrt_nr(piv);
+    const T sq = piv * rs;
+    // A[r][j] of my row and row j of my columns, before this step's update
+    const T arj = shfl_d(a[qj], r + 16 * gj);
+    T ajc[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) ajc[q] = shfl_d(a[q], j + 16 * g);
+    const T lrj = (r == j) ? sq : arj * rs;  // L[r][j] (r >= j)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int c = g + 4 * q;
+      if (c > j) a[q] = (r > j) ? a[q] - lrj * (ajc[q] * rs) : a[q];
+      if (c == j) a[q] = (r >= j) ? lrj : a[q];
+    }
+    // row j of X is final after scaling, then eliminated from the rows below
+#pragma unroll
+    for (int q = 0; q < 4; ++q) x[q] = (r == j) ? x[q] * rs : x[q];
+    T xjc[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) xjc[q] = shfl_d(x[q], j + 16 * g);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) x[q] = (r > j) ? x[q] - lrj * xjc[q] : x[q];
     T zj;
     if (!SAMPLE) {
-      zj = rlane(yr, j) * inv;
+      zj = rlane(yr, j) * rs;
     } else {
       // conditional simulation: rows of J are solved (w = z), rows of B take
       // w = xi and emit y = L_jj xi - v, v being the eliminated part so far
       const int R = kTile * k + j;
       const T vj = rlane(yr, j);
       if (R < mi) {
-        zj = vj * inv;
+        zj = vj * rs;
       } else {
         const T xj = sm.xi[R];
         zj = xj;
         if (r == j) *ysim = sq * xj - vj;
       }
     }
-    yr = (r == j) ? zj : (r > j ? yr - a[j] * zj : yr);
-#pragma unroll
-    for (int c = j + 1; c < 16; ++c) {
-      T lcj = rlane(a[j], c);
-      a[c] = a[c] - a[j] * lcj;
-    }
+    yr = (r == j) ? zj : (r > j ? yr - lrj * zj : yr);
   }
-  pivot_out = a[r];
+  // pivot L_rr lives in lane (r, r % 4), register r / 4
+  T mine = a[0];
+#pragma unroll
+  for (int q = 1; q < 4; ++q) mine = ((r >> 2) == q) ? a[q] : mine;
+  pivot_out = shfl_d(mine, r + 16 * (r & 3));
   z_out = yr;
-  // L to LDS (row-major, reusing the diagonal buffer), then X = L^{-1} with
-  // lane r owning column r and reading L by broadcast; x[k] = 0 above the
-  // diagonal.  One wave writes and reads, so waiting for its own LDS writes
-  // orders them.
-  if (lane < 16) {
+  // -X^T in B-operand layout: element X[a][b] at opoff(a, b)
 #pragma unroll
-    for (int c = 0; c < 16; ++c) sm.diag[r * 16 + c] = (c <= r) ? a[c] : T(0);
-  }
-  __builtin_amdgcn_s_waitcnt(0);
-  __builtin_amdgcn_wave_barrier();
-  T x[16];
+  for (int q = 0; q < 4; ++q) sm.negM[opoff<T>(r, g + 4 * q)] = -x[q];
+}
+
+template <typename T, int NTHR, class SM>
+__device__ void gen_column(SM& sm, int tid, int j, int nt, int nA, int d, int two_nu, T sigma2, T tau2) {
+  // one work item = (tile i, lane l): the 4 entries of accumulator registers
+  // t = 0..3, which share the point 16i + l%16 (read once) and differ in the
+  // point 16j + row(l/16, t)
+  const int total = (nt - j) * 64;
+  for (int e = tid; e < total; e += NTHR) {
+    const int i = j + (e >> 6);
+    const int l = e & 63;
+    const int pb = kTile * i + (l & 15);
+    const int pbc = pb < nA ? pb : 0;
+    T r2[4];
+    int pa[4];
 #pragma unroll
-  for (int rr = 0; rr < 16; ++rr) {
-    T acc = (rr == r) ? T(1) : T(0);
+    for (int t = 0; t < 4; ++t) {
+      pa[t] = kTile * j + MF<T>::row(l >> 4, t);
+      r2[t] = T(0);
+    }
+    int pac[4];
 #pragma unroll
-    for (int kk = 0; kk < rr; ++kk) acc = acc - sm.diag[rr * 16 + kk] * x[kk];
-    x[rr] = acc * invd[rr];
-  }
-  // M = X^T: row r of M is column r of X, held here.  Store -M.
-  if (lane < 16) {
+    for (int t = 0; t < 4; ++t) pac[t] = pa[t] < nA ? pa[t] : 0;
+    for (int k = 0; k < d; ++k) {
+      const T zbk = sm.z[pbc * d + k];
 #pragma unroll
-    for (int cc = 0; cc < 16; ++cc) sm.negM[opoff<T>(cc, r)] = -x[cc];
+      for (int t = 0; t < 4; ++t) {
+        const T df = sm.z[pac[t] * d + k] - zbk;
+        r2[t] += df * df;
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      T v;
+      if (pa[t] >= nA || pb >= nA) {
+        v = (pa[t] == pb) ? T(-1) : T(0);
+      } else {
+        v = -(sigma2 * matern<T>(t_sqrt(r2[t]), two_nu));
+        if (pa[t] == pb) v -= tau2;
+      }
+      sm.panel[256 * i + 64 * t + l] = v;
+    }
   }
 }
 
-
-// Stage tile column j of G = -Sigma_A^T blocks into sm.panel in accumulator
-// order: tile i (i >= j) entry (register t, lane l) holds
-// -Sigma(point 16i + l%16, point 16j + row(l/16, t)), with tau^2 on the
-// diagonal and identity rows/columns past the joint size.
-template <typename T, int NTHR, class SM>
-__device__ void gen_column(SM& sm, int tid, int j, int nt, int nA, int d, int two_nu, T sigma2,
-                           T tau2) {
-  const int total = (nt - j) * 256;
-  for (int e = tid; e < total; e += NTHR) {
-    const int i = j + (e >> 8);
-    const int r8 = e & 255;
-    const int t = r8 >> 6, l = r8 & 63;
-    const int pb = kTile * i + (l & 15);
-    const int pa = kTile * j + MF<T>::row(l >> 4, t);
-    T v;
-    if (pa >= nA || pb >= nA) {
-      v = (pa == pb) ? T(-1) : T(0);
-    } else {
-      T r2 = T(0);
-      for (int k = 0; k < d; ++k) {
-        T df = sm.z[pa * d + k] - sm.z[pb * d + k];
-        r2 += df * df;
-      }
-      v = -(sigma2 * matern<T>(t_sqrt(r2), two_nu));
-      if (pa == pb) v -= tau2;
+// Forward-solve update of the observations below tile row k:
+// y_rho -= L[rho][16k..16k+15] z_k, four rows per lane as independent chains.
+template <typename T, class SM>
+__device__ __forceinline__ void y_update(SM& sm, int lane, int k, int nt) {
+  T zk[16];
+#pragma unroll
+  for (int c = 0; c < 16; ++c) zk[c] = sm.zk[c];
+  const int r0 = kTile * (k + 1), r1 = kTile * nt;
+  for (int base = r0; base < r1; base += 256) {
+    T v[4];
+    int rho[4];
+#pragma unroll
+    for (int it = 0; it < 4; ++it) {
+      rho[it] = base + lane + 64 * it;
+      v[it] = rho[it] < r1 ? sm.yv[rho[it]] : T(0);
     }
-    sm.panel[256 * i + r8] = v;
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+#pragma unroll
+      for (int it = 0; it < 4; ++it) {
+        const int rr = rho[it] < r1 ? rho[it] : r0;
+        v[it] -= sm.panel[256 * (rr >> 4) + opoff<T>(rr & 15, c)] * zk[c];
+      }
+    }
+#pragma unroll
+    for (int it = 0; it < 4; ++it)
+      if (rho[it] < r1) sm.yv[rho[it]] = v[it];
   }
 }
 
@@ -233,13 +314,16 @@ template <typename T, int NTM, int NTHR, bool GRAD, bool SAMPLE, class SM>
 __device__ void panel_wave(SM& sm, int lane, int nt, int mi, int nA, int d, int two_nu, T sigma2, T tau2, T tau,
                            double& ld_acc, double& q_acc, int& bad, int& low, double* yout) {
   const T diag0 = sigma2 + tau2;
+  SBV_PROF_DECL
   for (int j = 0; j < nt; ++j) {
     gen_column<T, NTHR>(sm, lane, j, nt, nA, d, two_nu, sigma2, tau2);
     __syncthreads();  // G1
     __syncthreads();  // G2
   }
+  SBV_PROF(0, true);
   for (int k = 0; k < nt; ++k) {
     __syncthreads();  // S1: diagonal tile published
+    SBV_PROF(1, true);
     T piv, zr, ysim = T(0);
     factor_diag<T, SAMPLE>(sm, lane, k, nA - kTile * k, diag0, tau, piv, zr, bad, low, mi, &ysim);
     const int rowg = kTile * k + lane;
@@ -252,16 +336,12 @@ __device__ void panel_wave(SM& sm, int lane, int nt, int mi, int nA, int d, int 
         q_acc += (double)zr * (double)zr;
       }
     }
+    SBV_PROF(2, true);
     __syncthreads();  // S2: -L_kk^{-T} and z_k published
     __syncthreads();  // S3: column k of L published
-    for (int rho = kTile * (k + 1) + lane; rho < kTile * nt; rho += 64) {
-      const T* P = sm.panel + 256 * (rho >> 4);
-      const int rr = rho & 15;
-      T v = sm.yv[rho];
-#pragma unroll
-      for (int c = 0; c < 16; ++c) v -= P[opoff<T>(rr, c)] * sm.zk[c];
-      sm.yv[rho] = v;
-    }
+    SBV_PROF(3, true);
+    y_update<T>(sm, lane, k, nt);
+    SBV_PROF(4, true);
   }
 }
 
@@ -310,14 +390,7 @@ __device__ void panel_wave_la(SM& sm, int lane, int nt, int mi, int nA, int d, i
   __syncthreads();  // P0: step 0 factored
   for (int k = 0; k < nt; ++k) {
     __syncthreads();  // S3: column k of L published
-    for (int rho = kTile * (k + 1) + lane; rho < kTile * nt; rho += 64) {
-      const T* P = sm.panel + 256 * (rho >> 4);
-      const int rr = rho & 15;
-      T v = sm.yv[rho];
-#pragma unroll
-      for (int c = 0; c < 16; ++c) v -= P[opoff<T>(rr, c)] * sm.zk[c];
-      sm.yv[rho] = v;
-    }
+    y_update<T>(sm, lane, k, nt);
     if (k + 1 < nt) factor_step(k + 1);
     __syncthreads();  // S4: trailing update and next diagonal done
   }
@@ -484,6 +557,7 @@ __device__ void worker_waves(SM& sm, int wk, int lane, int nt, int mi, int nA, i
 #pragma unroll
     for (int t = 0; t < 4; ++t) acc[s][t] = T(0);
   }
+  SBV_PROF_DECL
   for (int j = 0; j < nt; ++j) {
     refresh_slots<SLOTS>(ti, tj);
     gen_column<T, NTHR>(sm, 64 * (wk + 1) + lane, j, nt, nA, d, two_nu, sigma2, tau2);
@@ -498,6 +572,7 @@ __device__ void worker_waves(SM& sm, int wk, int lane, int nt, int mi, int nA, i
     }
     __syncthreads();  // G2: staging area free
   }
+  SBV_PROF(8, wk == 0);
   for (int k = 0; k < nt; ++k) {
     refresh_slots<SLOTS>(ti, tj);
 #pragma unroll
@@ -508,7 +583,9 @@ __device__ void worker_waves(SM& sm, int wk, int lane, int nt, int mi, int nA, i
       }
     }
     __syncthreads();  // S1
+    SBV_PROF(9, wk == 0);
     __syncthreads();  // S2
+    SBV_PROF(10, wk == 0);
     // column-k TRSM: L_ik = A_ik L_kk^{-T}, published in operand layout
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
@@ -527,7 +604,9 @@ __device__ void worker_waves(SM& sm, int wk, int lane, int nt, int mi, int nA, i
         for (int t = 0; t < 4; ++t) acc[s][t] = -sm.negM[opoff<T>(MF<T>::row(g, t), cl)];
       }
     }
+    SBV_PROF(11, wk == 0);
     __syncthreads();  // S3
+    SBV_PROF(12, wk == 0);
     // trailing update G_ij += L_jk L_ik^T
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
@@ -540,6 +619,7 @@ __device__ void worker_waves(SM& sm, int wk, int lane, int nt, int mi, int nA, i
         acc[s] = o;
       }
     }
+    SBV_PROF(13, wk == 0);
   }
   if (!GRAD) return;
   // ---- adjoint solves L^T X = R, right-hand sides in chunks of 32 columns
@@ -651,6 +731,9 @@ __global__ __launch_bounds__(NW * 64) void k_block_loglik(const SetDesc* __restr
     }
     if (tid == 0) sm.la_flag = -1;
     __syncthreads();
+#ifdef SBV_PHASE_PROFILE
+    if (tid == 0) atomicAdd(&g_phase[14], 1ull);  // blocks processed
+#endif
 
     if (wave == 0) {
       double ld_acc = 0.0, q_acc = 0.0;
@@ -927,6 +1010,15 @@ hipError_t launch_contract(int prec, int v, int grid, const SetDesc* sets, const
 #undef SBV_CALL
   return hipErrorInvalidValue;
 }
+
+#ifdef SBV_PHASE_PROFILE
+hipError_t read_phase_profile(unsigned long long* out) {
+  hipError_t e = hipMemcpyFromSymbol(out, HIP_SYMBOL(g_phase), sizeof(unsigned long long) * 16);
+  if (e) return e;
+  unsigned long long z[16] = {};
+  return hipMemcpyToSymbol(HIP_SYMBOL(g_phase), z, sizeof(z));
+}
+#endif
 
 int max_grid(int prec, int v) {
   (void)prec;

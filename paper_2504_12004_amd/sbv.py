@@ -51,6 +51,13 @@ def lib():
         return _LIB
     if not os.path.exists(_LIB_PATH):
         raise RuntimeError(f"{_LIB_PATH} is missing: build it with paper_2504_12004_amd/build.py")
+    # PyTorch (when installed) carries its own copy of the HIP runtime under a
+    # different file name; importing it first makes the process use that one
+    # runtime for both torch and this library.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = C.CDLL(_LIB_PATH)
     sig = {
         "sbv_last_error": (C.c_char_p, []),

@@ -10,13 +10,13 @@ OUT=gpurun_out/prof
 mkdir -p $OUT
 echo "[prof] kernel trace"
 timeout -k 10 400 rocprofv3 --kernel-trace --stats -d $OUT/trace -o bench -- \
-  python3 bench.py --steps 10 --warmup 2 --no-cpu-baseline > $OUT/trace_bench.json 2> $OUT/trace_bench.err || exit $?
+  python3 bench.py --steps 10 --warmup 2 --no-cpu-baseline --fit-evals 0 > $OUT/trace_bench.json 2> $OUT/trace_bench.err || exit $?
 echo "[prof] FETCH_SIZE"
 timeout -s KILL 400 rocprofv3 --pmc FETCH_SIZE -d $OUT/fetch -o bench -- \
-  python3 bench.py --steps 3 --warmup 1 --no-cpu-baseline > $OUT/fetch_bench.json 2> $OUT/fetch_bench.err || exit $?
+  python3 bench.py --steps 3 --warmup 1 --no-cpu-baseline --fit-evals 0 > $OUT/fetch_bench.json 2> $OUT/fetch_bench.err || exit $?
 echo "[prof] WRITE_SIZE"
 timeout -s KILL 400 rocprofv3 --pmc WRITE_SIZE -d $OUT/write -o bench -- \
-  python3 bench.py --steps 3 --warmup 1 --no-cpu-baseline > $OUT/write_bench.json 2> $OUT/write_bench.err || exit $?
+  python3 bench.py --steps 3 --warmup 1 --no-cpu-baseline --fit-evals 0 > $OUT/write_bench.json 2> $OUT/write_bench.err || exit $?
 echo "[prof] copy calibration"
 timeout -s KILL 200 rocprofv3 --pmc FETCH_SIZE -d $OUT/copy_fetch -o copy -- python3 bench.py --copy-calibration > $OUT/copy1.json 2>&1 || exit $?
 timeout -s KILL 200 rocprofv3 --pmc WRITE_SIZE -d $OUT/copy_write -o copy -- python3 bench.py --copy-calibration > $OUT/copy2.json 2>&1 || exit $?
