@@ -97,6 +97,12 @@ def main():
         sbv.sbv_blocks_set_y(B, xi)
     torch.cuda.synchronize()
 
+    # per size bucket, pick the fastest kernel variant and schedule (setup, not timed)
+    tuned = {}
+    for name, prec in (("fp64", sbv.SBV_FP64), ("fp32", sbv.SBV_FP32)):
+        tuned[name] = [int(t) for t in sbv.sbv_autotune([B], theta_true, two_nu, prec, reps=3)]
+    log(f"autotuned tiles per bucket: {tuned}")
+
     thetas = synth.perturbed_thetas(theta_true, w["n_theta"], w["theta_seed"])
     th_d = torch.tensor(thetas, dtype=torch.float64, device=dev)
     out = torch.empty(max(args.steps, 1) + args.warmup + 8, dtype=torch.float64, device=dev)
@@ -190,6 +196,7 @@ def main():
             "fp32_fallback_blocks": int(fb),
             "grad_fp64_evals_per_s": grad_rate,
             "build_seconds": t_build,
+            "autotuned_tiles": tuned,
             "fits": fits,
         },
     }
@@ -223,13 +230,20 @@ def fit_legs(B, sbv, theta_true, two_nu, w, max_evals):
 
 
 def traffic(path):
-    """Per-launch HBM bytes of the dominant kernel from a counter summary
-    (FETCH_SIZE + WRITE_SIZE, each scaled by the plain-copy calibration), or
-    None when no summary for the current kernel is given."""
-    if not path or not os.path.exists(path):
+    """Per-launch HBM bytes of the dominant kernel from the committed counter
+    summary (FETCH_SIZE + WRITE_SIZE, each scaled by the plain-copy
+    calibration), or None when there is none or it was taken from kernel
+    sources other than the current ones."""
+    from paper_2504_12004_amd import profiling
+    if path is None:
+        path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                            "k_block_loglik_uneven_1m_traffic.json")
+    if not os.path.exists(path):
         return None
     with open(path) as f:
         t = json.load(f)
+    if t.get("kernel_source_hash") != profiling.kernel_source_hash():
+        return None
     return t.get("bytes_per_launch")
 
 

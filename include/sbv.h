@@ -266,11 +266,13 @@ sbv_status sbv_blocks_terms(sbv_blocks h, double* terms);
  * Measurement hooks (used by the benchmark).  sbv_timing_enable(1) makes every
  * subsequent evaluation bracket each kernel-variant launch with HIP events on
  * the launch stream; sbv_timing_read sums the elapsed milliseconds and launch
- * counts per variant for one precision (arrays of length sbv_timing_read's
- * *n_variants, at most 16; synchronises the device).  sbv_timing_enable(0)
- * discards the records.  sbv_plan_flops reports, per variant, the algorithmic
- * FLOP sum_i (nA_i^3/3 + nA_i^2) of one evaluation of these sets
- * (nA_i = m_i + b_i) and each variant's tile capacity in 16-row tiles.
+ * counts per size bucket for one precision (arrays of length sbv_timing_read's
+ * *n_variants, at most 16; synchronises the device).  A size bucket holds the
+ * blocks whose smallest fitting kernel variant has that index.
+ * sbv_timing_enable(0) discards the records.  sbv_plan_flops reports, per size
+ * bucket, the algorithmic FLOP sum_i (nA_i^3/3 + nA_i^2) of one evaluation of
+ * these sets (nA_i = m_i + b_i) and the tile capacity (16-row tiles) of the
+ * FP64 kernel launched for it, which the autotuner may have raised.
  */
 sbv_status sbv_timing_enable(int32_t on);
 sbv_status sbv_timing_read(int32_t prec, int32_t* n_variants, double* ms_total, int64_t* launches);

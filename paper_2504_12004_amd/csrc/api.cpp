@@ -327,7 +327,7 @@ sbv_status run_plan_grad(Plan* P, int32_t prec, hipStream_t s) {
 // result in P->out.
 sbv_status run_plan(Plan* P, int32_t prec, hipStream_t s) {
   for (auto& B : P->buckets) {
-    TimedLaunch tl{prec == SBV_FP32 ? 1 : 0, B.use(prec == SBV_FP32 ? 1 : 0), nullptr, nullptr};
+    TimedLaunch tl{prec == SBV_FP32 ? 1 : 0, B.variant, nullptr, nullptr};  // keyed by size bucket
     if (g_timing) {
       HIP_TRY(hipEventCreate(&tl.a));
       HIP_TRY(hipEventCreate(&tl.b));
@@ -805,8 +805,10 @@ sbv_status sbv_plan_flops(const sbv_blocks* sets, int32_t n_sets, const int32_t*
       flops[variant_for(sets[s]->joint[b])] += nA * nA * nA / 3.0 + nA * nA;
     }
   if (n_buckets) *n_buckets = nv;
-  if (variant_of_bucket)
+  if (variant_of_bucket) {
     for (int v = 0; v < nv; ++v) variant_of_bucket[v] = variant(v).ntm;
+    for (const auto& B : P->buckets) variant_of_bucket[B.variant] = variant(B.use(0)).ntm;
+  }
   return SBV_OK;
 }
 

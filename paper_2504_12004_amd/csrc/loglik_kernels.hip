@@ -164,7 +164,7 @@ __device__ __forceinline__ float shfl_d(float v, int src) { return __shfl(v, src
 // is raised for a non-positive or non-finite pivot and `low` for a pivot at or
 // below tau * original diagonal (the FP32 fallback test).
 template <typename T, bool SAMPLE = false, class SM>
-__device__ void factor_diag(SM& sm, int lane, int k, int nreal, T diag0, T tau, T& pivot_out,
+__device__ __forceinline__ void factor_diag(SM& sm, int lane, int k, int nreal, T diag0, T tau, T& pivot_out,
                             T& z_out, int& bad, int& low, int mi = 0, T* ysim = nullptr) {
   const int r = lane & 15, g = lane >> 4;
   T a[4], x[4];
@@ -233,7 +233,7 @@ __device__ void factor_diag(SM& sm, int lane, int k, int nreal, T diag0, T tau, 
 }
 
 template <typename T, int NTHR, class SM>
-__device__ void gen_column(SM& sm, int tid, int j, int nt, int nA, int d, int two_nu, T sigma2, T tau2) {
+__device__ __forceinline__ void gen_column(SM& sm, int tid, int j, int nt, int nA, int d, int two_nu, T sigma2, T tau2) {
   // one work item = (tile i, lane l): the 4 entries of accumulator registers
   // t = 0..3, which share the point 16i + l%16 (read once) and differ in the
   // point 16j + row(l/16, t)
@@ -311,7 +311,7 @@ __device__ __forceinline__ void y_update(SM& sm, int lane, int k, int nt) {
 // also keeps all of z and then takes part in the adjoint solves (barriers,
 // right-hand-side set-up and write-back).
 template <typename T, int NTM, int NTHR, bool GRAD, bool SAMPLE, class SM>
-__device__ void panel_wave(SM& sm, int lane, int nt, int mi, int nA, int d, int two_nu, T sigma2, T tau2, T tau,
+__device__ __forceinline__ void panel_wave(SM& sm, int lane, int nt, int mi, int nA, int d, int two_nu, T sigma2, T tau2, T tau,
                            double& ld_acc, double& q_acc, int& bad, int& low, double* yout) {
   const T diag0 = sigma2 + tau2;
   SBV_PROF_DECL
@@ -365,7 +365,7 @@ __device__ __forceinline__ void refresh_slots(int* ti, int* tj) {
 // of step k and publishes it with an LDS flag; the panel wave factors it while
 // the workers finish step k.  Two barriers per step instead of three.
 template <typename T, int NTM, int NTHR, class SM>
-__device__ void panel_wave_la(SM& sm, int lane, int nt, int mi, int nA, int d, int two_nu, T sigma2, T tau2, T tau,
+__device__ __forceinline__ void panel_wave_la(SM& sm, int lane, int nt, int mi, int nA, int d, int two_nu, T sigma2, T tau2, T tau,
                               double& ld_acc, double& q_acc, int& bad, int& low) {
   const T diag0 = sigma2 + tau2;
   for (int j = 0; j < nt; ++j) {
@@ -397,7 +397,7 @@ __device__ void panel_wave_la(SM& sm, int lane, int nt, int mi, int nA, int d, i
 }
 
 template <typename T, int NTM, int NWK, int NTHR, class SM>
-__device__ void worker_waves_la(SM& sm, int wk, int lane, int nt, int nA, int d, int two_nu, T sigma2, T tau2) {
+__device__ __forceinline__ void worker_waves_la(SM& sm, int wk, int lane, int nt, int nA, int d, int two_nu, T sigma2, T tau2) {
   typedef typename MF<T>::acc acc_t;
   constexpr int NTT = NTM * (NTM + 1) / 2;
   constexpr int SLOTS = (NTT + NWK - 1) / NWK;
@@ -525,7 +525,7 @@ __device__ void rhs_writeback(SM& sm, int tid, int ch, int mi, int nA, int bi, T
 // the finished factor stays in the slots (diagonal slots take L_kk^{-1}) and
 // the workers run the backward solves L^T X = R chunk by chunk.
 template <typename T, int NTM, int NWK, int NTHR, bool GRAD, class SM>
-__device__ void worker_waves(SM& sm, int wk, int lane, int nt, int mi, int nA, int bi, int d, int two_nu,
+__device__ __forceinline__ void worker_waves(SM& sm, int wk, int lane, int nt, int mi, int nA, int bi, int d, int two_nu,
                              T sigma2, T tau2, T* gout) {
   typedef typename MF<T>::acc acc_t;
   constexpr int NTT = NTM * (NTM + 1) / 2;
@@ -675,7 +675,7 @@ __device__ void worker_waves(SM& sm, int wk, int lane, int nt, int mi, int nA, i
 // The panel wave's share of the adjoint solves: same barriers, plus its part
 // of the set-up and write-back loops.
 template <typename T, int NTHR, class SM>
-__device__ void panel_adjoint(SM& sm, int lane, int nt, int mi, int nA, int bi, T* gout) {
+__device__ __forceinline__ void panel_adjoint(SM& sm, int lane, int nt, int mi, int nA, int bi, T* gout) {
   const int nch = (bi + 1 + kChunk - 1) / kChunk;
   __syncthreads();  // B0
   for (int r = lane; r < nt * kTile; r += NTHR) sm.gv[r] = T(0);
