@@ -121,7 +121,21 @@ struct Bucket {
   DevBuf<int> dcount;      // device copy of count
   DevBuf<WorkItem> fb_items;
   DevBuf<int> fb_count;
+  // large path (joint sizes above the register capacity): items are processed
+  // in windows of nb with a workspace of nb slots (L_RP panel and z_P, FP64-sized)
+  bool large = false;
+  int nb = 0;
+  DevBuf<double> W, Z;
 };
+
+// Workspace slots of the large path (each kLargeW + kLargeZ elements, about
+// 0.5 MB in FP64): windows of this many blocks share one workspace.  The
+// environment variable SBV_LARGE_WINDOW overrides it for new plans.
+int large_window() {
+  const char* e = std::getenv("SBV_LARGE_WINDOW");
+  const int v = e ? std::atoi(e) : 0;
+  return v > 0 ? v : 2048;
+}
 
 struct Plan {
   std::vector<sbv_blocks> sets;
@@ -194,7 +208,8 @@ sbv_status get_plan(const sbv_blocks* sets, int32_t n_sets, const int32_t* two_n
   P->two_nu.assign(two_nu, two_nu + n_sets);
   std::vector<SetDesc> hd(n_sets);
   int off = 0;
-  std::vector<std::vector<std::pair<int32_t, WorkItem>>> per(n_variants());
+  // one list per register variant, plus the large path last
+  std::vector<std::vector<std::pair<int32_t, WorkItem>>> per(n_variants() + 1);
   for (int s = 0; s < n_sets; ++s) {
     sbv_blocks h = sets[s];
     SetDesc& D = hd[s];
@@ -214,7 +229,11 @@ sbv_status get_plan(const sbv_blocks* sets, int32_t n_sets, const int32_t* two_n
     off += h->d + 2;
     for (int64_t b = 0; b < h->K; ++b) {
       int v = variant_for(h->joint[b]);
-      if (v < 0) return fail(SBV_E_INVAL, "block joint size exceeds the supported maximum");
+      if (v < 0) {
+        const int mi = (int)(h->nn_ptr[b + 1] - h->nn_ptr[b]);
+        if (large_prefix(h->joint[b], mi) < 0) return fail(SBV_E_INVAL, "block joint size not supported");
+        v = n_variants();
+      }
       per[v].push_back({h->joint[b], WorkItem{s, (int32_t)b}});
     }
   }
@@ -226,7 +245,7 @@ sbv_status get_plan(const sbv_blocks* sets, int32_t n_sets, const int32_t* two_n
   HIP_TRY(P->out.alloc(n_sets));
   HIP_TRY(P->bad.alloc(n_sets));
   // longest buckets first
-  for (int v = n_variants() - 1; v >= 0; --v) {
+  for (int v = n_variants(); v >= 0; --v) {
     if (per[v].empty()) continue;
     auto& L = per[v];
     std::stable_sort(L.begin(), L.end(), [](const auto& a, const auto& b) { return a.first > b.first; });
@@ -241,6 +260,12 @@ sbv_status get_plan(const sbv_blocks* sets, int32_t n_sets, const int32_t* two_n
     HIP_TRY(hipMemcpy(B.dcount.p, &B.count, sizeof(int), hipMemcpyHostToDevice));
     HIP_TRY(B.fb_items.alloc(it.size()));
     HIP_TRY(B.fb_count.alloc(1));
+    if (v == n_variants()) {
+      B.large = true;
+      B.nb = std::min(B.count, large_window());
+      HIP_TRY(B.W.alloc((size_t)B.nb * kLargeW));
+      HIP_TRY(B.Z.alloc((size_t)B.nb * kLargeZ));
+    }
     // SBV_LOOKAHEAD=1 selects the lookahead schedule for new plans (the
     // autotuner may change it per bucket later)
     const char* la = std::getenv("SBV_LOOKAHEAD");
@@ -264,13 +289,11 @@ std::vector<TimedLaunch> g_timed;
 
 // Pivot threshold of the FP32 path: a block whose FP32 pivot falls to or below
 // this fraction of the original diagonal is recomputed in FP64.  The
-// environment variable SBV_PIV_TAU overrides it (read once).
+// environment variable SBV_PIV_TAU overrides it (read at every queued
+// evaluation; a captured graph keeps the value of its capture).
 double piv_tau() {
-  static double t = [] {
-    const char* e = std::getenv("SBV_PIV_TAU");
-    return e ? std::atof(e) : 1e-4;
-  }();
-  return t;
+  const char* e = std::getenv("SBV_PIV_TAU");
+  return e ? std::atof(e) : 1e-4;
 }
 #define g_piv_tau piv_tau()
 
@@ -303,6 +326,10 @@ sbv_status ensure_adjoint(Plan* P) {
 // factor + adjoint-solve kernel, then the contraction kernel; FP32 blocks that
 // trip the pivot test are redone in FP64 (both kernels).
 sbv_status run_plan_grad(Plan* P, int32_t prec, hipStream_t s) {
+  for (const auto& B : P->buckets)
+    if (B.large)
+      return fail(SBV_E_INVAL, "the gradient supports joint sizes up to " +
+                                   std::to_string(variant(n_variants() - 1).ntm * kTile));
   sbv_status st = ensure_adjoint(P);
   if (st) return st;
   const int pk = prec == SBV_FP32 ? 1 : 0;
@@ -334,8 +361,14 @@ sbv_status run_plan(Plan* P, int32_t prec, hipStream_t s) {
       HIP_TRY(hipEventRecord(tl.a, s));
     }
     const int pk = prec == SBV_FP32 ? 1 : 0;
-    HIP_TRY(launch_loglik(pk, B.use(pk), B.count, P->dsets.p, P->theta.p, B.items.p, B.dcount.p,
-                          pk ? g_piv_tau : 0.0, s, false, B.la[pk]));
+    if (B.large) {
+      for (int off = 0; off < B.count; off += B.nb)
+        HIP_TRY(launch_large(pk, std::min(B.nb, B.count - off), P->dsets.p, P->theta.p, B.items.p, B.dcount.p,
+                             pk ? g_piv_tau : 0.0, LargeArgs{off, B.nb, B.W.p, B.Z.p}, s));
+    } else {
+      HIP_TRY(launch_loglik(pk, B.use(pk), B.count, P->dsets.p, P->theta.p, B.items.p, B.dcount.p,
+                            pk ? g_piv_tau : 0.0, s, false, B.la[pk]));
+    }
     if (g_timing) {
       HIP_TRY(hipEventRecord(tl.b, s));
       g_timed.push_back(tl);
@@ -343,8 +376,16 @@ sbv_status run_plan(Plan* P, int32_t prec, hipStream_t s) {
     if (prec == SBV_FP32) {
       HIP_TRY(launch_zero_int(B.fb_count.p, 1, s));
       HIP_TRY(launch_flag_compact(P->dsets.p, B.items.p, B.dcount.p, B.fb_items.p, B.fb_count.p, s));
-      int grid = std::min(B.count, max_grid(0, B.use(0)));
-      HIP_TRY(launch_loglik(0, B.use(0), grid, P->dsets.p, P->theta.p, B.fb_items.p, B.fb_count.p, 0.0, s));
+      if (B.large) {
+        // the flagged count is only known on the device: every window is
+        // queued and windows past it exit at once
+        for (int off = 0; off < B.count; off += B.nb)
+          HIP_TRY(launch_large(0, std::min(B.nb, B.count - off), P->dsets.p, P->theta.p, B.fb_items.p,
+                               B.fb_count.p, 0.0, LargeArgs{off, B.nb, B.W.p, B.Z.p}, s));
+      } else {
+        int grid = std::min(B.count, max_grid(0, B.use(0)));
+        HIP_TRY(launch_loglik(0, B.use(0), grid, P->dsets.p, P->theta.p, B.fb_items.p, B.fb_count.p, 0.0, s));
+      }
     }
   }
   HIP_TRY(launch_reduce(P->dsets.p, (int)P->sets.size(), nullptr, P->out.p, P->bad.p, s));
@@ -398,7 +439,7 @@ extern "C" {
 
 const char* sbv_last_error(void) { return g_err.c_str(); }
 
-int32_t sbv_max_joint_size(void) { return variant(n_variants() - 1).ntm * kTile; }
+int32_t sbv_max_joint_size(void) { return kTile * (kLargeNTM + kMaxPrefix); }
 
 sbv_status sbv_blocks_import(const double* X, const double* y, int64_t n, int32_t d, int64_t K,
                              const int64_t* block_ptr, const int64_t* block_pts, const int64_t* nn_ptr,
@@ -549,6 +590,9 @@ sbv_status sbv_loglik_grad(const sbv_blocks* sets, int32_t n_sets, const double*
 // than the highest level among the blocks holding its conditioning points, so
 // every block of a level only reads observations of lower levels.
 static sbv_status ensure_sampler(sbv_blocks h, int32_t two_nu) {
+  if (h->max_joint > variant(n_variants() - 1).ntm * kTile)
+    return fail(SBV_E_INVAL, "the conditional simulator supports joint sizes up to " +
+                                 std::to_string(variant(n_variants() - 1).ntm * kTile));
   if (h->sample_levels.empty()) {
     const int64_t K = h->K;
     std::vector<int32_t> block_of(h->n);
@@ -651,6 +695,11 @@ sbv_status sbv_autotune(const sbv_blocks* sets, int32_t n_sets, const int32_t* t
   HIP_TRY(hipEventCreate(&b));
   int bi = 0;
   for (auto& B : P->buckets) {
+    if (B.large) {  // one kernel pair, nothing to choose
+      if (chosen_tiles) chosen_tiles[bi] = kLargeNTM + kMaxPrefix;
+      ++bi;
+      continue;
+    }
     // the bucket's own variant is the smallest that fits; candidates are it and all larger ones
     const int base = B.variant;
     float best = INFINITY;
@@ -774,7 +823,7 @@ sbv_status sbv_timing_enable(int32_t on) {
 
 sbv_status sbv_timing_read(int32_t prec, int32_t* n_variants_out, double* ms_total, int64_t* launches) {
   HIP_TRY(hipDeviceSynchronize());
-  const int nv = n_variants();
+  const int nv = n_variants() + 1;  // size buckets: register variants, then the large path
   if (n_variants_out) *n_variants_out = nv;
   for (int v = 0; v < nv; ++v) {
     if (ms_total) ms_total[v] = 0.0;
@@ -797,17 +846,20 @@ sbv_status sbv_plan_flops(const sbv_blocks* sets, int32_t n_sets, const int32_t*
   Plan* P = nullptr;
   st = get_plan(sets, n_sets, two_nu, &P);
   if (st) return st;
-  const int nv = n_variants();
-  for (int v = 0; v < nv; ++v) flops[v] = 0.0;
+  const int nv = n_variants();  // register variants; bucket nv is the large path
+  for (int v = 0; v <= nv; ++v) flops[v] = 0.0;
   for (int s = 0; s < n_sets; ++s)
     for (int64_t b = 0; b < sets[s]->K; ++b) {
       const double nA = sets[s]->joint[b];
-      flops[variant_for(sets[s]->joint[b])] += nA * nA * nA / 3.0 + nA * nA;
+      const int v = variant_for(sets[s]->joint[b]);
+      flops[v < 0 ? nv : v] += nA * nA * nA / 3.0 + nA * nA;
     }
-  if (n_buckets) *n_buckets = nv;
+  if (n_buckets) *n_buckets = nv + 1;
   if (variant_of_bucket) {
     for (int v = 0; v < nv; ++v) variant_of_bucket[v] = variant(v).ntm;
-    for (const auto& B : P->buckets) variant_of_bucket[B.variant] = variant(B.use(0)).ntm;
+    variant_of_bucket[nv] = kLargeNTM + kMaxPrefix;
+    for (const auto& B : P->buckets)
+      if (!B.large) variant_of_bucket[B.variant] = variant(B.use(0)).ntm;
   }
   return SBV_OK;
 }
@@ -843,10 +895,16 @@ sbv_status sbv_internal_make_handle(const double* X, const double* y, int64_t n,
   h->nn_idx.assign(nn_idx, nn_idx + h->nnz);
   h->joint.resize(K);
   for (int64_t r = 0; r < K; ++r) {
-    int64_t j = (nn_ptr[r + 1] - nn_ptr[r]) + (block_ptr[r + 1] - block_ptr[r]);
+    const int64_t mi = nn_ptr[r + 1] - nn_ptr[r];
+    int64_t j = mi + (block_ptr[r + 1] - block_ptr[r]);
     if (j > sbv_max_joint_size())
       return fail(SBV_E_INVAL, "block " + std::to_string(r) + " has joint size " + std::to_string(j) +
                                    " above the supported maximum");
+    if (variant_for((int)j) < 0 && large_prefix((int)j, (int)mi) < 0)
+      return fail(SBV_E_INVAL, "block " + std::to_string(r) + " has joint size " + std::to_string(j) +
+                                   " but only " + std::to_string(mi) +
+                                   " conditioning points; above 272 the first 16 * (ceil(size / 16) - 17) "
+                                   "joint points must be conditioning points");
     h->joint[r] = (int32_t)j;
     h->max_joint = std::max<int32_t>(h->max_joint, (int32_t)j);
   }

@@ -164,8 +164,9 @@ __device__ __forceinline__ float shfl_d(float v, int src) { return __shfl(v, src
 // is raised for a non-positive or non-finite pivot and `low` for a pivot at or
 // below tau * original diagonal (the FP32 fallback test).
 template <typename T, bool SAMPLE = false, class SM>
-__device__ __forceinline__ void factor_diag(SM& sm, int lane, int k, int nreal, T diag0, T tau, T& pivot_out,
-                            T& z_out, int& bad, int& low, int mi = 0, T* ysim = nullptr) {
+__device__ __forceinline__ void factor_diag(SM& sm, T* negM_out, int lane, int k, int nreal, T diag0, T tau,
+                                            T& pivot_out, T& z_out, int& bad, int& low, int mi = 0,
+                                            T* ysim = nullptr) {
   const int r = lane & 15, g = lane >> 4;
   T a[4], x[4];
 #pragma unroll
@@ -229,17 +230,18 @@ __device__ __forceinline__ void factor_diag(SM& sm, int lane, int k, int nreal, 
   z_out = yr;
   // -X^T in B-operand layout: element X[a][b] at opoff(a, b)
 #pragma unroll
-  for (int q = 0; q < 4; ++q) sm.negM[opoff<T>(r, g + 4 * q)] = -x[q];
+  for (int q = 0; q < 4; ++q) negM_out[opoff<T>(r, g + 4 * q)] = -x[q];
 }
 
 template <typename T, int NTHR, class SM>
-__device__ __forceinline__ void gen_column(SM& sm, int tid, int j, int nt, int nA, int d, int two_nu, T sigma2, T tau2) {
-  // one work item = (tile i, lane l): the 4 entries of accumulator registers
-  // t = 0..3, which share the point 16i + l%16 (read once) and differ in the
-  // point 16j + row(l/16, t)
-  const int total = (nt - j) * 64;
+__device__ __forceinline__ void gen_column(SM& sm, int tid, int j, int i0, int nt, int nA, int d, int two_nu,
+                                           T sigma2, T tau2) {
+  // tiles (i, j) for i = i0..nt-1.  One work item = (tile i, lane l): the 4
+  // entries of accumulator registers t = 0..3, which share the point
+  // 16i + l%16 (read once) and differ in the point 16j + row(l/16, t)
+  const int total = (nt - i0) * 64;
   for (int e = tid; e < total; e += NTHR) {
-    const int i = j + (e >> 6);
+    const int i = i0 + (e >> 6);
     const int l = e & 63;
     const int pb = kTile * i + (l & 15);
     const int pbc = pb < nA ? pb : 0;
@@ -275,14 +277,15 @@ __device__ __forceinline__ void gen_column(SM& sm, int tid, int j, int nt, int n
   }
 }
 
-// Forward-solve update of the observations below tile row k:
-// y_rho -= L[rho][16k..16k+15] z_k, four rows per lane as independent chains.
+// Forward-solve update of the observations in rows r0..16nt-1 with the column
+// tile of L staged in the panel: y_rho -= L[rho][16k..16k+15] z_k, four rows
+// per lane as independent chains.
 template <typename T, class SM>
-__device__ __forceinline__ void y_update(SM& sm, int lane, int k, int nt) {
+__device__ __forceinline__ void y_update(SM& sm, int lane, int r0, int nt) {
   T zk[16];
 #pragma unroll
   for (int c = 0; c < 16; ++c) zk[c] = sm.zk[c];
-  const int r0 = kTile * (k + 1), r1 = kTile * nt;
+  const int r1 = kTile * nt;
   for (int base = r0; base < r1; base += 256) {
     T v[4];
     int rho[4];
@@ -305,27 +308,46 @@ __device__ __forceinline__ void y_update(SM& sm, int lane, int k, int nt) {
   }
 }
 
+// Stage column tile k of a large block's prefix panel (nt tiles of L below
+// the prefix, operand layout, written by the prefix kernel) and z_k.
+template <typename T, int NTHR, class SM>
+__device__ __forceinline__ void load_prefix(SM& sm, int tid, int k, int nt, const T* W, const T* zp) {
+  const T* src = W + (int64_t)k * kLargeNTM * 256;
+  for (int e = tid; e < nt * 256; e += NTHR) sm.panel[e] = src[e];
+  if (tid < kTile) sm.zk[tid] = zp[kTile * k + tid];
+}
+
 // Panel wave: for every tile step factors the diagonal tile, solves the 16
 // entries of z, accumulates the trailing log-pivots and z^2 in FP64, and
 // applies the forward-solve update to the observations below.  In GRAD mode it
 // also keeps all of z and then takes part in the adjoint solves (barriers,
 // right-hand-side set-up and write-back).
-template <typename T, int NTM, int NTHR, bool GRAD, bool SAMPLE, class SM>
-__device__ __forceinline__ void panel_wave(SM& sm, int lane, int nt, int mi, int nA, int d, int two_nu, T sigma2, T tau2, T tau,
-                           double& ld_acc, double& q_acc, int& bad, int& low, double* yout) {
+template <typename T, int NTM, int NTHR, bool GRAD, bool SAMPLE, bool PRE, class SM>
+__device__ __forceinline__ void panel_wave(SM& sm, int lane, int nt, int mi, int nA, int d, int two_nu, T sigma2,
+                                           T tau2, T tau, double& ld_acc, double& q_acc, int& bad, int& low,
+                                           double* yout, int p, const T* Wp, const T* zp) {
   const T diag0 = sigma2 + tau2;
   SBV_PROF_DECL
   for (int j = 0; j < nt; ++j) {
-    gen_column<T, NTHR>(sm, lane, j, nt, nA, d, two_nu, sigma2, tau2);
+    gen_column<T, NTHR>(sm, lane, j, j, nt, nA, d, two_nu, sigma2, tau2);
     __syncthreads();  // G1
     __syncthreads();  // G2
+  }
+  if (PRE) {
+    // large block: y -= L_RP z_P, one prefix column tile at a time
+    for (int k = 0; k < p; ++k) {
+      load_prefix<T, NTHR>(sm, lane, k, nt, Wp, zp);
+      __syncthreads();  // P1: prefix column k staged
+      y_update<T>(sm, lane, 0, nt);
+      __syncthreads();  // P2: staging area free
+    }
   }
   SBV_PROF(0, true);
   for (int k = 0; k < nt; ++k) {
     __syncthreads();  // S1: diagonal tile published
     SBV_PROF(1, true);
     T piv, zr, ysim = T(0);
-    factor_diag<T, SAMPLE>(sm, lane, k, nA - kTile * k, diag0, tau, piv, zr, bad, low, mi, &ysim);
+    factor_diag<T, SAMPLE>(sm, sm.negM, lane, k, nA - kTile * k, diag0, tau, piv, zr, bad, low, mi, &ysim);
     const int rowg = kTile * k + lane;
     if (SAMPLE && lane < 16 && rowg >= mi && rowg < nA) yout[rowg - mi] = (double)ysim;
     if (lane < 16) {
@@ -340,7 +362,7 @@ __device__ __forceinline__ void panel_wave(SM& sm, int lane, int nt, int mi, int
     __syncthreads();  // S2: -L_kk^{-T} and z_k published
     __syncthreads();  // S3: column k of L published
     SBV_PROF(3, true);
-    y_update<T>(sm, lane, k, nt);
+    y_update<T>(sm, lane, kTile * (k + 1), nt);
     SBV_PROF(4, true);
   }
 }
@@ -369,14 +391,14 @@ __device__ __forceinline__ void panel_wave_la(SM& sm, int lane, int nt, int mi, 
                               double& ld_acc, double& q_acc, int& bad, int& low) {
   const T diag0 = sigma2 + tau2;
   for (int j = 0; j < nt; ++j) {
-    gen_column<T, NTHR>(sm, lane, j, nt, nA, d, two_nu, sigma2, tau2);
+    gen_column<T, NTHR>(sm, lane, j, j, nt, nA, d, two_nu, sigma2, tau2);
     __syncthreads();  // G1
     __syncthreads();  // G2
   }
   auto factor_step = [&](int k) {
     while (__atomic_load_n(&sm.la_flag, __ATOMIC_ACQUIRE) < k) __builtin_amdgcn_s_sleep(1);
     T piv, zr;
-    factor_diag<T>(sm, lane, k, nA - kTile * k, diag0, tau, piv, zr, bad, low);
+    factor_diag<T>(sm, sm.negM, lane, k, nA - kTile * k, diag0, tau, piv, zr, bad, low);
     const int rowg = kTile * k + lane;
     if (lane < 16) {
       sm.zk[lane] = zr;
@@ -390,7 +412,7 @@ __device__ __forceinline__ void panel_wave_la(SM& sm, int lane, int nt, int mi, 
   __syncthreads();  // P0: step 0 factored
   for (int k = 0; k < nt; ++k) {
     __syncthreads();  // S3: column k of L published
-    y_update<T>(sm, lane, k, nt);
+    y_update<T>(sm, lane, kTile * (k + 1), nt);
     if (k + 1 < nt) factor_step(k + 1);
     __syncthreads();  // S4: trailing update and next diagonal done
   }
@@ -428,7 +450,7 @@ __device__ __forceinline__ void worker_waves_la(SM& sm, int wk, int lane, int nt
   }
   for (int j = 0; j < nt; ++j) {
     refresh_slots<SLOTS>(ti, tj);
-    gen_column<T, NTHR>(sm, 64 * (wk + 1) + lane, j, nt, nA, d, two_nu, sigma2, tau2);
+    gen_column<T, NTHR>(sm, 64 * (wk + 1) + lane, j, j, nt, nA, d, two_nu, sigma2, tau2);
     __syncthreads();  // G1
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
@@ -524,9 +546,10 @@ __device__ void rhs_writeback(SM& sm, int tid, int ch, int mi, int nA, int bi, T
 // run the column TRSMs and trailing MFMA updates of every step.  In GRAD mode
 // the finished factor stays in the slots (diagonal slots take L_kk^{-1}) and
 // the workers run the backward solves L^T X = R chunk by chunk.
-template <typename T, int NTM, int NWK, int NTHR, bool GRAD, class SM>
-__device__ __forceinline__ void worker_waves(SM& sm, int wk, int lane, int nt, int mi, int nA, int bi, int d, int two_nu,
-                             T sigma2, T tau2, T* gout) {
+template <typename T, int NTM, int NWK, int NTHR, bool GRAD, bool PRE, class SM>
+__device__ __forceinline__ void worker_waves(SM& sm, int wk, int lane, int nt, int mi, int nA, int bi, int d,
+                                             int two_nu, T sigma2, T tau2, T* gout, int p, const T* Wp,
+                                             const T* zp) {
   typedef typename MF<T>::acc acc_t;
   constexpr int NTT = NTM * (NTM + 1) / 2;
   constexpr int SLOTS = (NTT + NWK - 1) / NWK;
@@ -560,7 +583,7 @@ __device__ __forceinline__ void worker_waves(SM& sm, int wk, int lane, int nt, i
   SBV_PROF_DECL
   for (int j = 0; j < nt; ++j) {
     refresh_slots<SLOTS>(ti, tj);
-    gen_column<T, NTHR>(sm, 64 * (wk + 1) + lane, j, nt, nA, d, two_nu, sigma2, tau2);
+    gen_column<T, NTHR>(sm, 64 * (wk + 1) + lane, j, j, nt, nA, d, two_nu, sigma2, tau2);
     __syncthreads();  // G1: column j staged
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
@@ -571,6 +594,26 @@ __device__ __forceinline__ void worker_waves(SM& sm, int wk, int lane, int nt, i
       }
     }
     __syncthreads();  // G2: staging area free
+  }
+  if (PRE) {
+    // large block: G += L_RP L_RP^T, one prefix column tile at a time
+    for (int k = 0; k < p; ++k) {
+      load_prefix<T, NTHR>(sm, 64 * (wk + 1) + lane, k, nt, Wp, zp);
+      __syncthreads();  // P1
+      refresh_slots<SLOTS>(ti, tj);
+#pragma unroll
+      for (int s = 0; s < SLOTS; ++s) {
+        if (tj[s] >= 0) {
+          const T* Pj = sm.panel + 256 * tj[s];
+          const T* Pi = sm.panel + 256 * ti[s];
+          acc_t o = acc[s];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) o = MF<T>::mma(Pj[64 * q + lane], Pi[64 * q + lane], o);
+          acc[s] = o;
+        }
+      }
+      __syncthreads();  // P2
+    }
   }
   SBV_PROF(8, wk == 0);
   for (int k = 0; k < nt; ++k) {
@@ -692,42 +735,66 @@ __device__ __forceinline__ void panel_adjoint(SM& sm, int lane, int nt, int mi, 
   for (int r = lane; r < nA; r += NTHR) gout[nA + r] = sm.gv[r];
 }
 
-template <typename T, int NTM, int NW, bool GRAD, bool SAMPLE = false, bool LA = false>
+// PRE: large-block mode.  The block's first p = ceil(nA/16) - NTM tile rows
+// were eliminated by k_block_prefix, which left L_RP and z_P in the workspace
+// window L; this kernel factors the trailing NTM tiles (local point l is joint
+// point l + 16p) after applying the p prefix updates.
+template <typename T, int NTM, int NW, bool GRAD, bool SAMPLE = false, bool LA = false, bool PRE = false>
 __global__ __launch_bounds__(NW * 64) void k_block_loglik(const SetDesc* __restrict__ sets,
                                                           const double* __restrict__ theta,
                                                           const WorkItem* __restrict__ items,
                                                           const int* __restrict__ count,
-                                                          double piv_tau) {
+                                                          double piv_tau, LargeArgs L) {
+  static_assert(!PRE || (!GRAD && !SAMPLE && !LA && NTM == kLargeNTM), "large-block mode is forward only");
   __shared__ Smem<T, NTM, GRAD> sm;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int total = *count;
+  const int total = PRE ? min(max(*count - L.off, 0), L.nb) : *count;
+  const WorkItem* itm = PRE ? items + L.off : items;
 
   for (int it = blockIdx.x; it < total; it += gridDim.x) {
-    const WorkItem w = items[it];
+    const WorkItem w = itm[it];
     const SetDesc S = sets[w.set];
     const int d = S.d;
     const double* th = theta + S.theta_off;
     const int b0 = S.bptr[w.block], b1 = S.bptr[w.block + 1];
     const int64_t n0 = S.nptr[w.block], n1 = S.nptr[w.block + 1];
     const int mi = (int)(n1 - n0), bi = b1 - b0, nA = mi + bi;
-    const int nt = (nA + kTile - 1) / kTile;
+    int pre = 0;
+    if (PRE) {
+      pre = (nA + kTile - 1) / kTile - NTM;
+      if (pre < 1 || pre > kMaxPrefix || kTile * pre > mi) {
+        // not a large-path block (the host never queues one): mark it failed
+        if (tid == 0) {
+          S.llb[w.block] = -__builtin_inf();
+          S.flag[w.block] = 2;
+        }
+        continue;
+      }
+    }
+    const int off = kTile * pre;
+    const int nAl = nA - off, mil = mi - off;  // local joint size and conditioning count
+    const int nt = (nAl + kTile - 1) / kTile;
     const T sigma2 = T(exp(th[d]));
     const T tau2 = T(exp(th[d + 1]));
     T* gout = GRAD ? reinterpret_cast<T*>(S.qbuf) + S.qoff[w.block] : nullptr;
+    const T* Wp = PRE ? reinterpret_cast<const T*>(L.W) + (int64_t)it * kLargeW : nullptr;
+    const T* zp = PRE ? reinterpret_cast<const T*>(L.z) + (int64_t)it * kLargeZ : nullptr;
 
     // gather A = J u B (J first): scaled coordinates and observations
-    for (int e = tid; e < nA * d; e += NW * 64) {
-      int p = e / d, k = e - p * d;
-      int pos = p < mi ? S.nidx[n0 + p] : b0 + (p - mi);
-      sm.z[p * d + k] = T(S.X[(int64_t)pos * d + k] * exp(-th[k]));
+    for (int e = tid; e < nAl * d; e += NW * 64) {
+      int pl = e / d, k = e - pl * d;
+      int pa = pl + off;
+      int pos = pa < mi ? S.nidx[n0 + pa] : b0 + (pa - mi);
+      sm.z[pl * d + k] = T(S.X[(int64_t)pos * d + k] * exp(-th[k]));
     }
-    for (int p = tid; p < nt * kTile; p += NW * 64) {
+    for (int pl = tid; pl < nt * kTile; pl += NW * 64) {
+      const int pa = pl + off;
       T v = T(0);
-      if (p < nA && (!SAMPLE || p < mi)) v = T(S.y[p < mi ? S.nidx[n0 + p] : b0 + (p - mi)]);
-      sm.yv[p] = v;
-      if (SAMPLE) sm.xi[p] = (p >= mi && p < nA) ? T(S.xi[b0 + (p - mi)]) : T(0);
+      if (pl < nAl && (!SAMPLE || pa < mi)) v = T(S.y[pa < mi ? S.nidx[n0 + pa] : b0 + (pa - mi)]);
+      sm.yv[pl] = v;
+      if (SAMPLE) sm.xi[pl] = (pa >= mi && pl < nAl) ? T(S.xi[b0 + (pa - mi)]) : T(0);
     }
     if (tid == 0) sm.la_flag = -1;
     __syncthreads();
@@ -742,8 +809,9 @@ __global__ __launch_bounds__(NW * 64) void k_block_loglik(const SetDesc* __restr
         panel_wave_la<T, NTM, NW * 64>(sm, lane, nt, mi, nA, d, S.two_nu, sigma2, tau2, T(piv_tau), ld_acc, q_acc,
                                        bad, low);
       else
-        panel_wave<T, NTM, NW * 64, GRAD, SAMPLE>(sm, lane, nt, mi, nA, d, S.two_nu, sigma2, tau2, T(piv_tau),
-                                                  ld_acc, q_acc, bad, low, S.y_out + b0);
+        panel_wave<T, NTM, NW * 64, GRAD, SAMPLE, PRE>(sm, lane, nt, mil, nAl, d, S.two_nu, sigma2, tau2,
+                                                       T(piv_tau), ld_acc, q_acc, bad, low, S.y_out + b0, pre,
+                                                       Wp, zp);
 #pragma unroll
       for (int off = 8; off >= 1; off >>= 1) {
         ld_acc += __shfl_xor(ld_acc, off, 16);
@@ -754,15 +822,260 @@ __global__ __launch_bounds__(NW * 64) void k_block_loglik(const SetDesc* __restr
         double l = -0.5 * (q_acc + 2.0 * ld_acc + (double)bi * kLog2Pi);
         if (bad) l = -__builtin_inf();
         S.llb[w.block] = l;
-        S.flag[w.block] = fb;
+        S.flag[w.block] = PRE ? (S.flag[w.block] | fb) : fb;  // PRE: keep the prefix kernel's flags
       }
       if (GRAD) panel_adjoint<T, NW * 64>(sm, lane, nt, mi, nA, bi, gout);
     } else {
       if (LA)
         worker_waves_la<T, NTM, NW - 1, NW * 64>(sm, wave - 1, lane, nt, nA, d, S.two_nu, sigma2, tau2);
       else
-        worker_waves<T, NTM, NW - 1, NW * 64, GRAD>(sm, wave - 1, lane, nt, mi, nA, bi, d, S.two_nu, sigma2, tau2,
-                                                    gout);
+        worker_waves<T, NTM, NW - 1, NW * 64, GRAD, PRE>(sm, wave - 1, lane, nt, mil, nAl, bi, d, S.two_nu,
+                                                         sigma2, tau2, gout, pre, Wp, zp);
+    }
+    __syncthreads();
+  }
+}
+
+// ---- large blocks: elimination of the prefix --------------------------------
+// A block whose joint size nA exceeds 16 * kLargeNTM is split as A = [P; R]:
+// P the first p = ceil(nA/16) - kLargeNTM tile rows (conditioning points only,
+// 16p <= m_i) and R the last kLargeNTM tiles.  Block Cholesky gives
+//   L = [L_PP, 0; L_RP, chol(T)],  L_RP = Sigma_RP L_PP^{-T},
+//   T = Sigma_RR - L_RP L_RP^T,  z_P = L_PP^{-1} y_P,  z_R = chol(T)^{-1} (y_R - L_RP z_P),
+// and every pivot and z entry of the block's own rows lies in the R part, so
+// the block term of Alg. 5 follows from T and y_R - L_RP z_P alone.  This
+// kernel factors Sigma_PP once into register tiles, keeps the inverses of its
+// diagonal tiles in LDS, and builds L_RP in chunks of kLargeNTM - p tile rows:
+// each chunk's Sigma_RP tiles are generated into the slots below P and
+// eliminated column by column against the resident L_PP.  L_RP goes to the
+// workspace tile by tile in the operand layout of the register kernel's panel,
+// z_P beside it; k_block_loglik<..., PRE> consumes both.
+template <typename T>
+struct SmemP {
+  T z[kLargeNTM * kTile * kMaxDim];  // scaled coordinates: P, then the current chunk of R
+  T yv[kLargeNTM * kTile];           // observations of P, overwritten by the forward solve
+  T panel[kLargeNTM * 256];          // generation staging / column k of L (operand layout)
+  T diag[256];                       // diagonal tile to factor (row-major)
+  T negMs[kMaxPrefix * 256];         // -(L_kk^{-T}) of every diagonal tile of P
+  T zk[kTile];
+  T xi[1];  // unused: factor_diag's simulation branch is not instantiated here
+};
+
+// Scaled coordinates (and, with yv, observations) of local points [lo, hi);
+// local point l is joint point l + shift (J first); points past nA are zero.
+template <typename T, int NTHR>
+__device__ __forceinline__ void gather_points(T* z, T* yv, int tid, int lo, int hi, int shift, int d, int mi,
+                                              int nA, const SetDesc& S, int b0, int64_t n0, const double* th) {
+  for (int e = tid; e < (hi - lo) * d; e += NTHR) {
+    const int pl = lo + e / d, k = e % d;
+    const int pa = pl + shift;
+    T v = T(0);
+    if (pa < nA) {
+      const int pos = pa < mi ? S.nidx[n0 + pa] : b0 + (pa - mi);
+      v = T(S.X[(int64_t)pos * d + k] * exp(-th[k]));
+    }
+    z[pl * d + k] = v;
+  }
+  if (yv)
+    for (int pl = lo + tid; pl < hi; pl += NTHR) {
+      const int pa = pl + shift;
+      yv[pl] = pa < nA ? T(S.y[pa < mi ? S.nidx[n0 + pa] : b0 + (pa - mi)]) : T(0);
+    }
+}
+
+// Panel wave of the prefix kernel: factors the diagonal tiles of P (first
+// chunk only), solves z_P and writes it out; otherwise it takes part in the
+// gathers and the generation and keeps the barrier count of the workers.
+template <typename T, int NTHR, class SM>
+__device__ __forceinline__ void prefix_panel_wave(SM& sm, int lane, int p, int c, const SetDesc& S, int b0,
+                                                  int64_t n0, int mi, int nA, int d, const double* th, T sigma2,
+                                                  T tau2, T tau, int& bad, int& low, T* zout) {
+  const T diag0 = sigma2 + tau2;
+  const int nch = (kLargeNTM + c - 1) / c;
+  for (int ch = 0; ch < nch; ++ch) {
+    const int r0 = ch * c, cc = min(c, kLargeNTM - r0), ntl = p + cc, nAl = nA - kTile * r0;
+    gather_points<T, NTHR>(sm.z, (T*)nullptr, lane, kTile * p, kTile * ntl, kTile * r0, d, mi, nA, S, b0, n0,
+                           th);
+    __syncthreads();  // C0: chunk coordinates staged
+    for (int j = 0; j < p; ++j) {
+      gen_column<T, NTHR>(sm, lane, j, ch == 0 ? j : p, ntl, nAl, d, S.two_nu, sigma2, tau2);
+      __syncthreads();  // G1
+      __syncthreads();  // G2
+    }
+    for (int k = 0; k < p; ++k) {
+      if (ch == 0) {
+        __syncthreads();  // S1: diagonal tile published
+        T piv, zr;
+        factor_diag<T>(sm, sm.negMs + 256 * k, lane, k, kTile, diag0, tau, piv, zr, bad, low);
+        if (lane < kTile) {
+          sm.zk[lane] = zr;
+          zout[kTile * k + lane] = zr;
+        }
+        __syncthreads();  // S2: inverse of the diagonal tile published
+        __syncthreads();  // S3: column k of L published
+        y_update<T>(sm, lane, kTile * (k + 1), p);
+      } else {
+        __syncthreads();  // S3
+        __syncthreads();  // S4
+      }
+    }
+  }
+}
+
+// Worker waves of the prefix kernel.  Slots are numbered over the full
+// kLargeNTM x kLargeNTM tile grid exactly as in the register kernel (p + c =
+// kLargeNTM), so tiles of P stay in the same slots across chunks while the
+// slots of rows p.. are regenerated for every chunk of R.
+template <typename T, int NTM, int NWK, int NTHR, class SM>
+__device__ __forceinline__ void prefix_worker_waves(SM& sm, int wk, int lane, int p, int c, const SetDesc& S,
+                                                    int b0, int64_t n0, int mi, int nA, int d, const double* th,
+                                                    T sigma2, T tau2, T* Wout) {
+  typedef typename MF<T>::acc acc_t;
+  constexpr int NTT = NTM * (NTM + 1) / 2;
+  constexpr int SLOTS = (NTT + NWK - 1) / NWK;
+  const int g = lane >> 4;
+  const int cl = lane & 15;
+  const int tid = 64 * (wk + 1) + lane;
+  int ti[SLOTS], tj[SLOTS];
+#pragma unroll
+  for (int s = 0; s < SLOTS; ++s) {
+    int t = s * NWK + wk;
+    int i = -1, j = -1;
+    if (t < NTT) {
+      j = 0;
+      while (t >= NTM - j) {
+        t -= NTM - j;
+        ++j;
+      }
+      i = j + t;
+    }
+    ti[s] = __builtin_amdgcn_readfirstlane(i);
+    tj[s] = __builtin_amdgcn_readfirstlane(j);
+  }
+  acc_t acc[SLOTS];
+#pragma unroll
+  for (int s = 0; s < SLOTS; ++s) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc[s][t] = T(0);
+  }
+  const int nch = (NTM + c - 1) / c;
+  for (int ch = 0; ch < nch; ++ch) {
+    const int r0 = ch * c, cc = min(c, NTM - r0), ntl = p + cc, nAl = nA - kTile * r0;
+    gather_points<T, NTHR>(sm.z, (T*)nullptr, tid, kTile * p, kTile * ntl, kTile * r0, d, mi, nA, S, b0, n0, th);
+    __syncthreads();  // C0
+    for (int j = 0; j < p; ++j) {
+      refresh_slots<SLOTS>(ti, tj);
+      const int i0 = ch == 0 ? j : p;
+      gen_column<T, NTHR>(sm, tid, j, i0, ntl, nAl, d, S.two_nu, sigma2, tau2);
+      __syncthreads();  // G1: column j staged
+#pragma unroll
+      for (int s = 0; s < SLOTS; ++s) {
+        if (tj[s] == j && ti[s] >= i0 && ti[s] < ntl) {
+          const T* src = sm.panel + 256 * ti[s];
+#pragma unroll
+          for (int t = 0; t < 4; ++t) acc[s][t] = src[64 * t + lane];
+        }
+      }
+      __syncthreads();  // G2
+    }
+    for (int k = 0; k < p; ++k) {
+      refresh_slots<SLOTS>(ti, tj);
+      const T* nM = sm.negMs + 256 * k;
+      if (ch == 0) {
+#pragma unroll
+        for (int s = 0; s < SLOTS; ++s) {
+          if (ti[s] == k && tj[s] == k) {
+#pragma unroll
+            for (int t = 0; t < 4; ++t) sm.diag[cl * 16 + MF<T>::row(g, t)] = -acc[s][t];
+          }
+        }
+        __syncthreads();  // S1
+        __syncthreads();  // S2
+      } else {
+        // L_PP column k is final: publish it for this chunk's updates
+#pragma unroll
+        for (int s = 0; s < SLOTS; ++s) {
+          if (tj[s] == k && ti[s] > k && ti[s] < p) {
+            T* P = sm.panel + 256 * ti[s];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) P[opoff<T>(MF<T>::row(g, t), cl)] = acc[s][t];
+          }
+        }
+      }
+      // column-k solves: rows of P (first chunk) and of the current chunk of R
+#pragma unroll
+      for (int s = 0; s < SLOTS; ++s) {
+        if (tj[s] == k && ti[s] < ntl && (ch == 0 ? ti[s] > k : ti[s] >= p)) {
+          acc_t o = {T(0), T(0), T(0), T(0)};
+#pragma unroll
+          for (int q = 0; q < 4; ++q) o = MF<T>::mma(acc[s][q], nM[64 * q + lane], o);
+          acc[s] = o;
+          T* P = sm.panel + 256 * ti[s];
+#pragma unroll
+          for (int t = 0; t < 4; ++t) P[opoff<T>(MF<T>::row(g, t), cl)] = o[t];
+        }
+      }
+      __syncthreads();  // S3: column k of L published
+      // L_RP tiles of this chunk to the workspace (contiguous, coalesced)
+      {
+        T* dst = Wout + ((int64_t)k * NTM + r0) * 256;
+        const T* src = sm.panel + 256 * p;
+        for (int e = tid - 64; e < cc * 256; e += NTHR - 64) dst[e] = src[e];
+      }
+      // trailing update restricted to columns of P (the R x R part is left to
+      // the register kernel)
+#pragma unroll
+      for (int s = 0; s < SLOTS; ++s) {
+        if (tj[s] > k && tj[s] < p && ti[s] < ntl && (ch == 0 || ti[s] >= p)) {
+          const T* Pj = sm.panel + 256 * tj[s];
+          const T* Pi = sm.panel + 256 * ti[s];
+          acc_t o = acc[s];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) o = MF<T>::mma(Pj[64 * q + lane], Pi[64 * q + lane], o);
+          acc[s] = o;
+        }
+      }
+      if (ch > 0) __syncthreads();  // S4: staging area free
+    }
+  }
+}
+
+template <typename T, int NW>
+__global__ __launch_bounds__(NW * 64) void k_block_prefix(const SetDesc* __restrict__ sets,
+                                                          const double* __restrict__ theta,
+                                                          const WorkItem* __restrict__ items,
+                                                          const int* __restrict__ count, double piv_tau,
+                                                          LargeArgs L) {
+  __shared__ SmemP<T> sm;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int total = min(max(*count - L.off, 0), L.nb);
+  for (int it = blockIdx.x; it < total; it += gridDim.x) {
+    const WorkItem w = items[L.off + it];
+    const SetDesc S = sets[w.set];
+    const int d = S.d;
+    const double* th = theta + S.theta_off;
+    const int b0 = S.bptr[w.block], b1 = S.bptr[w.block + 1];
+    const int64_t n0 = S.nptr[w.block], n1 = S.nptr[w.block + 1];
+    const int mi = (int)(n1 - n0), nA = mi + (b1 - b0);
+    const int p = (nA + kTile - 1) / kTile - kLargeNTM;
+    if (p < 1 || p > kMaxPrefix || kTile * p > mi) continue;  // never queued by the host
+    const int c = kLargeNTM - p;
+    const T sigma2 = T(exp(th[d]));
+    const T tau2 = T(exp(th[d + 1]));
+    T* Wout = reinterpret_cast<T*>(L.W) + (int64_t)it * kLargeW;
+    T* zout = reinterpret_cast<T*>(L.z) + (int64_t)it * kLargeZ;
+    gather_points<T, NW * 64>(sm.z, sm.yv, tid, 0, kTile * p, 0, d, mi, nA, S, b0, n0, th);
+    __syncthreads();
+    if (wave == 0) {
+      int bad = 0, low = 0;
+      prefix_panel_wave<T, NW * 64>(sm, lane, p, c, S, b0, n0, mi, nA, d, th, sigma2, tau2, T(piv_tau), bad, low,
+                                    zout);
+      if (lane == 0) S.flag[w.block] = (bad ? 2 : 0) | (low ? 1 : 0);
+    } else {
+      prefix_worker_waves<T, kLargeNTM, NW - 1, NW * 64>(sm, wave - 1, lane, p, c, S, b0, n0, mi, nA, d, th,
+                                                         sigma2, tau2, Wout);
     }
     __syncthreads();
   }
@@ -940,13 +1253,13 @@ static hipError_t launch_t(int grid, bool grad, bool la, const SetDesc* sets, co
                            const WorkItem* items, const int* count, double piv_tau, hipStream_t s) {
   if (la && !grad)
     hipLaunchKernelGGL((k_block_loglik<T, NTM, NW, false, false, true>), dim3(grid), dim3(NW * 64), 0, s, sets,
-                       theta, items, count, piv_tau);
+                       theta, items, count, piv_tau, LargeArgs{});
   else if (grad)
     hipLaunchKernelGGL((k_block_loglik<T, NTM, NW, true>), dim3(grid), dim3(NW * 64), 0, s, sets, theta, items,
-                       count, piv_tau);
+                       count, piv_tau, LargeArgs{});
   else
     hipLaunchKernelGGL((k_block_loglik<T, NTM, NW, false>), dim3(grid), dim3(NW * 64), 0, s, sets, theta, items,
-                       count, piv_tau);
+                       count, piv_tau, LargeArgs{});
   return hipGetLastError();
 }
 
@@ -954,7 +1267,7 @@ template <typename T, int NTM, int NW>
 static hipError_t launch_s(int grid, const SetDesc* sets, const double* theta, const WorkItem* items,
                            const int* count, hipStream_t s) {
   hipLaunchKernelGGL((k_block_loglik<T, NTM, NW, false, true>), dim3(grid), dim3(NW * 64), 0, s, sets, theta,
-                     items, count, 0.0);
+                     items, count, 0.0, LargeArgs{});
   return hipGetLastError();
 }
 
@@ -987,6 +1300,24 @@ hipError_t launch_loglik(int prec, int v, int grid, const SetDesc* sets, const d
   }
 #undef SBV_CALL
   return hipErrorInvalidValue;
+}
+
+template <typename T>
+static hipError_t launch_large_t(int grid, const SetDesc* sets, const double* theta, const WorkItem* items,
+                                 const int* count, double piv_tau, const LargeArgs& L, hipStream_t s) {
+  hipLaunchKernelGGL((k_block_prefix<T, 8>), dim3(grid), dim3(512), 0, s, sets, theta, items, count, piv_tau, L);
+  hipError_t e = hipGetLastError();
+  if (e) return e;
+  hipLaunchKernelGGL((k_block_loglik<T, kLargeNTM, 8, false, false, false, true>), dim3(grid), dim3(512), 0, s,
+                     sets, theta, items, count, piv_tau, L);
+  return hipGetLastError();
+}
+
+hipError_t launch_large(int prec, int grid, const SetDesc* sets, const double* theta, const WorkItem* items,
+                        const int* count, double piv_tau, const LargeArgs& L, hipStream_t s) {
+  if (grid <= 0) return hipSuccess;
+  if (prec == 0) return launch_large_t<double>(grid, sets, theta, items, count, piv_tau, L, s);
+  return launch_large_t<float>(grid, sets, theta, items, count, piv_tau, L, s);
 }
 
 hipError_t launch_sample(int v, int grid, const SetDesc* sets, const double* theta, const WorkItem* items,

@@ -45,6 +45,37 @@ struct Variant {
   int nw;
 };
 
+// Blocks whose joint size exceeds the register capacity of the largest
+// variant (kLargeNTM tiles) take the two-kernel path: the first
+// p = ceil(nA/16) - kLargeNTM tile rows (conditioning points, 16p <= m_i) are
+// eliminated by the prefix kernel, which writes the panel of L below them and
+// their part of z to a workspace; the trailing kLargeNTM tiles are then
+// factored by the register kernel after p streamed rank-16 updates.
+constexpr int kLargeNTM = 17;
+constexpr int kMaxPrefix = 15;  // joint sizes up to 16 * (kLargeNTM + kMaxPrefix) = 512
+constexpr int64_t kLargeW = (int64_t)kMaxPrefix * kLargeNTM * 256;  // panel elements per workspace slot
+constexpr int64_t kLargeZ = (int64_t)kMaxPrefix * kTile;            // z elements per workspace slot
+
+// Workspace window of one launch of the large-block kernels: they process
+// items[off + i] for i < min(*count - off, nb), item i using workspace slot i
+// (W + i * kLargeW, z + i * kLargeZ, elements of the kernel precision).
+struct LargeArgs {
+  int32_t off;
+  int32_t nb;
+  void* W;
+  void* z;
+};
+
+// Prefix length p of a block with joint size nA and m_i conditioning points
+// on the large path, or -1 when it does not qualify (fits a register variant,
+// exceeds 512, or the prefix would reach into the block's own points).
+inline int large_prefix(int nA, int mi) {
+  const int nt = (nA + kTile - 1) / kTile;
+  const int p = nt - kLargeNTM;
+  if (p < 1 || p > kMaxPrefix || kTile * p > mi) return -1;
+  return p;
+}
+
 // Launchers (kernels.hip).  `count` is a device int; the kernel loops over
 // items[blockIdx.x + k*gridDim.x] while the index is below *count.
 hipError_t launch_loglik(int prec, int variant, int grid, const SetDesc* sets, const double* theta,
@@ -64,6 +95,9 @@ hipError_t launch_flag_compact(const SetDesc* sets, const WorkItem* items, const
                                WorkItem* out_items, int* out_count, hipStream_t s);
 hipError_t launch_zero_int(int* p, int n, hipStream_t s);
 int max_grid(int prec, int variant);
+// Both kernels of the large path for one workspace window (prec 0 FP64, 1 FP32).
+hipError_t launch_large(int prec, int grid, const SetDesc* sets, const double* theta, const WorkItem* items,
+                        const int* count, double piv_tau, const LargeArgs& L, hipStream_t s);
 
 }  // namespace sbv
 
