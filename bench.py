@@ -47,6 +47,8 @@ def main():
                     help="only run a plain 1 GiB device copy (to scale HBM byte counters)")
     ap.add_argument("--fit-evals", type=int, default=300,
                     help="evaluation budget of each MLE fit leg (0 skips the fits)")
+    ap.add_argument("--large-steps", type=int, default=3,
+                    help="evaluations of the m = 400, n = 5e6 leg per precision (0 skips it)")
     ap.add_argument("--traffic-json", default=None,
                     help="JSON with measured per-launch HBM bytes of the dominant kernel")
     args = ap.parse_args()
@@ -170,6 +172,10 @@ def main():
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(B, X, sbv, theta_true, two_nu, args.cpu_seconds)
 
+    large = None
+    if args.large_steps > 0:
+        large = large_leg(sbv, torch, dev, stream, args.large_steps)
+
     res = {
         "metric": "SBV loglik evals/s (n=1M, m=200, FP64)",
         "value": 1000.0 / ms_step,
@@ -198,11 +204,61 @@ def main():
             "build_seconds": t_build,
             "autotuned_tiles": tuned,
             "fits": fits,
+            "m400_5m": large,
         },
     }
     if cpu is not None:
         res["cpu_baseline"] = cpu
     print(json.dumps(res), flush=True)
+
+
+def large_leg(sbv, torch, dev, stream, steps):
+    """The n = 5e6, d = 10, K = 2.5e5, m = 400 workload (joint sizes up to 460:
+    most blocks take the large path).  Forward log-likelihood only; y is the
+    standard-normal draw of the generator (the conditional simulator covers
+    joint sizes up to 272, and the timing does not depend on y)."""
+    from paper_2504_12004_amd import synth
+    w = synth.dataset("grad_5m")
+    X, theta, xi = w["X"], w["theta"], w["xi"]
+    d = X.shape[1]
+    t0 = time.perf_counter()
+    B = sbv.sbv_build_blocks(X, xi, np.exp(theta[:d]), w["K"], w["m"], method=sbv.SBV_KMEANS,
+                             lloyd_iters=w["lloyd_iters"], min_bs=w["min_bs"], max_bs=w["max_bs"], seed=w["seed"])
+    t_build = time.perf_counter() - t0
+    del X
+    two_nu = w["two_nu"]
+    th_d = torch.tensor(theta, dtype=torch.float64, device=dev)
+    out = torch.empty(steps + 2, dtype=torch.float64, device=dev)
+    flops, tiles = sbv.sbv_plan_flops(B, two_nu)
+    res = {"workload": "m400_5m: n=5e6 d=10 Matern-5/2 tau2=1e-4 kmeans K=2.5e5 (5..60) m=400",
+           "build_seconds": t_build, "blocks": B.K, "algorithmic_tflop_per_eval": float(np.sum(flops)) / 1e12,
+           "large_path_flop_share": float(flops[-1] / np.sum(flops)), "data": "y iid standard normal"}
+    vals = {}
+    for name, prec in (("fp64", sbv.SBV_FP64), ("fp32", sbv.SBV_FP32)):
+        sbv.sbv_loglik_dev(B, th_d, two_nu, out[0:1], prec, stream)
+        torch.cuda.synchronize()
+        sbv.sbv_timing_enable(True)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for i in range(steps):
+            sbv.sbv_loglik_dev(B, th_d, two_nu, out[1 + i:2 + i], prec, stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        kt, kl = sbv.sbv_timing_read(prec)
+        sbv.sbv_timing_enable(False)
+        vals[name] = float(out[1].item())
+        large_ms = kt[-1] / max(kl[-1], 1)
+        res[name] = {"evals_per_s": 1000.0 / ms, "ms_per_eval": ms,
+                     "large_bucket_ms": large_ms,
+                     "large_bucket_tflops": flops[-1] / (large_ms * 1e-3) / 1e12 if large_ms > 0 else None,
+                     "total_algorithmic_tflops": float(np.sum(flops)) / (ms * 1e-3) / 1e12,
+                     "fallback_blocks": int(sbv.sbv_blocks_fallback_count(B)) if prec == sbv.SBV_FP32 else 0}
+        log(f"m400_5m {name}: {ms:.1f} ms/eval, large bucket {large_ms:.1f} ms, "
+            f"{res[name]['total_algorithmic_tflops']:.2f} TFLOP/s algorithmic")
+    res["fp32_rel_diff_vs_fp64"] = abs(vals["fp32"] - vals["fp64"]) / abs(vals["fp64"])
+    B.free()
+    return res
 
 
 def fit_legs(B, sbv, theta_true, two_nu, w, max_evals):

@@ -23,8 +23,8 @@ import sys
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 KERNEL_SOURCES = ("paper_2504_12004_amd/csrc/loglik_kernels.hip", "paper_2504_12004_amd/csrc/sbv_internal.h",
                   "paper_2504_12004_amd/build.py")
-BENCH_ARGS = ["--steps", "10", "--warmup", "2", "--no-cpu-baseline", "--fit-evals", "0"]
-COUNTER_BENCH_ARGS = ["--steps", "3", "--warmup", "1", "--no-cpu-baseline", "--fit-evals", "0"]
+BENCH_ARGS = ["--steps", "10", "--warmup", "2", "--no-cpu-baseline", "--fit-evals", "0", "--large-steps", "0"]
+COUNTER_BENCH_ARGS = ["--steps", "3", "--warmup", "1", "--no-cpu-baseline", "--fit-evals", "0", "--large-steps", "0"]
 
 
 def kernel_source_hash():
