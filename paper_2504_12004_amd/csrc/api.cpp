@@ -125,7 +125,7 @@ struct Bucket {
   // in windows of nb with a workspace of nb slots (L_RP panel and z_P, FP64-sized)
   bool large = false;
   int nb = 0;
-  DevBuf<double> W, Z;
+  DevBuf<double> W, Z, Lpp;  // Lpp: the prefix factor, allocated with the adjoint buffers
 };
 
 // Workspace slots of the large path (each kLargeW + kLargeZ elements, about
@@ -319,6 +319,8 @@ sbv_status ensure_adjoint(Plan* P) {
   }
   HIP_TRY(hipMemcpy(P->dsets.p, P->hdesc.data(), sizeof(SetDesc) * ns, hipMemcpyHostToDevice));
   HIP_TRY(P->grad.alloc(P->theta_len));
+  for (auto& B : P->buckets)
+    if (B.large) HIP_TRY(B.Lpp.alloc((size_t)B.nb * kLargeL));
   return SBV_OK;
 }
 
@@ -326,14 +328,24 @@ sbv_status ensure_adjoint(Plan* P) {
 // factor + adjoint-solve kernel, then the contraction kernel; FP32 blocks that
 // trip the pivot test are redone in FP64 (both kernels).
 sbv_status run_plan_grad(Plan* P, int32_t prec, hipStream_t s) {
-  for (const auto& B : P->buckets)
-    if (B.large)
-      return fail(SBV_E_INVAL, "the gradient supports joint sizes up to " +
-                                   std::to_string(variant(n_variants() - 1).ntm * kTile));
   sbv_status st = ensure_adjoint(P);
   if (st) return st;
   const int pk = prec == SBV_FP32 ? 1 : 0;
   for (auto& B : P->buckets) {
+    if (B.large) {
+      for (int off = 0; off < B.count; off += B.nb)
+        HIP_TRY(launch_large_grad(pk, std::min(B.nb, B.count - off), P->dsets.p, P->theta.p, B.items.p,
+                                  B.dcount.p, pk ? g_piv_tau : 0.0, LargeArgs{off, B.nb, B.W.p, B.Z.p, B.Lpp.p},
+                                  s));
+      if (pk) {
+        HIP_TRY(launch_zero_int(B.fb_count.p, 1, s));
+        HIP_TRY(launch_flag_compact(P->dsets.p, B.items.p, B.dcount.p, B.fb_items.p, B.fb_count.p, s));
+        for (int off = 0; off < B.count; off += B.nb)
+          HIP_TRY(launch_large_grad(0, std::min(B.nb, B.count - off), P->dsets.p, P->theta.p, B.fb_items.p,
+                                    B.fb_count.p, 0.0, LargeArgs{off, B.nb, B.W.p, B.Z.p, B.Lpp.p}, s));
+      }
+      continue;
+    }
     HIP_TRY(launch_loglik(pk, B.variant, B.count, P->dsets.p, P->theta.p, B.items.p, B.dcount.p,
                           pk ? g_piv_tau : 0.0, s, true));
     HIP_TRY(launch_contract(pk, B.variant, B.count, P->dsets.p, P->theta.p, B.items.p, B.dcount.p, s));
@@ -364,7 +376,7 @@ sbv_status run_plan(Plan* P, int32_t prec, hipStream_t s) {
     if (B.large) {
       for (int off = 0; off < B.count; off += B.nb)
         HIP_TRY(launch_large(pk, std::min(B.nb, B.count - off), P->dsets.p, P->theta.p, B.items.p, B.dcount.p,
-                             pk ? g_piv_tau : 0.0, LargeArgs{off, B.nb, B.W.p, B.Z.p}, s));
+                             pk ? g_piv_tau : 0.0, LargeArgs{off, B.nb, B.W.p, B.Z.p, nullptr}, s));
     } else {
       HIP_TRY(launch_loglik(pk, B.use(pk), B.count, P->dsets.p, P->theta.p, B.items.p, B.dcount.p,
                             pk ? g_piv_tau : 0.0, s, false, B.la[pk]));
@@ -381,7 +393,7 @@ sbv_status run_plan(Plan* P, int32_t prec, hipStream_t s) {
         // queued and windows past it exit at once
         for (int off = 0; off < B.count; off += B.nb)
           HIP_TRY(launch_large(0, std::min(B.nb, B.count - off), P->dsets.p, P->theta.p, B.fb_items.p,
-                               B.fb_count.p, 0.0, LargeArgs{off, B.nb, B.W.p, B.Z.p}, s));
+                               B.fb_count.p, 0.0, LargeArgs{off, B.nb, B.W.p, B.Z.p, nullptr}, s));
       } else {
         int grid = std::min(B.count, max_grid(0, B.use(0)));
         HIP_TRY(launch_loglik(0, B.use(0), grid, P->dsets.p, P->theta.p, B.fb_items.p, B.fb_count.p, 0.0, s));

@@ -521,9 +521,11 @@ __device__ void rhs_init(SM& sm, int tid, int ch, int nt, int mi, int bi) {
 }
 
 // After the solves of one chunk: accumulate g = Q z_B, write e / Q columns of
-// this block to its slice of the adjoint buffer (e, g, then Q column-major).
+// this block to its slice of the adjoint buffer (e, g, then Q column-major,
+// column stride ld: the joint size; a large block's trailing part writes rows
+// from its prefix length on, through an offset `out`).
 template <typename T, int NTHR, class SM>
-__device__ void rhs_writeback(SM& sm, int tid, int ch, int mi, int nA, int bi, T* out) {
+__device__ void rhs_writeback(SM& sm, int tid, int ch, int mi, int nA, int bi, int ld, T* out) {
   for (int r = tid; r < nA; r += NTHR) {
     T gacc = sm.gv[r];
 #pragma unroll 4
@@ -535,7 +537,7 @@ __device__ void rhs_writeback(SM& sm, int tid, int ch, int mi, int nA, int bi, T
         out[r] = v;
       } else {
         gacc += v * sm.zfull[mi + col - 1];
-        out[(int64_t)(2 + col - 1) * nA + r] = v;
+        out[(int64_t)(2 + col - 1) * ld + r] = v;
       }
     }
     sm.gv[r] = gacc;
@@ -548,7 +550,7 @@ __device__ void rhs_writeback(SM& sm, int tid, int ch, int mi, int nA, int bi, T
 // the workers run the backward solves L^T X = R chunk by chunk.
 template <typename T, int NTM, int NWK, int NTHR, bool GRAD, bool PRE, class SM>
 __device__ __forceinline__ void worker_waves(SM& sm, int wk, int lane, int nt, int mi, int nA, int bi, int d,
-                                             int two_nu, T sigma2, T tau2, T* gout, int p, const T* Wp,
+                                             int two_nu, T sigma2, T tau2, T* gout, int ld, int p, const T* Wp,
                                              const T* zp) {
   typedef typename MF<T>::acc acc_t;
   constexpr int NTT = NTM * (NTM + 1) / 2;
@@ -709,16 +711,16 @@ __device__ __forceinline__ void worker_waves(SM& sm, int wk, int lane, int nt, i
       }
       __syncthreads();  // B3
     }
-    rhs_writeback<T, NTHR>(sm, tid, ch, mi, nA, bi, gout);
+    rhs_writeback<T, NTHR>(sm, tid, ch, mi, nA, bi, ld, gout);
     __syncthreads();  // B4
   }
-  for (int r = tid; r < nA; r += NTHR) gout[nA + r] = sm.gv[r];
+  for (int r = tid; r < nA; r += NTHR) gout[ld + r] = sm.gv[r];
 }
 
 // The panel wave's share of the adjoint solves: same barriers, plus its part
 // of the set-up and write-back loops.
 template <typename T, int NTHR, class SM>
-__device__ __forceinline__ void panel_adjoint(SM& sm, int lane, int nt, int mi, int nA, int bi, T* gout) {
+__device__ __forceinline__ void panel_adjoint(SM& sm, int lane, int nt, int mi, int nA, int bi, int ld, T* gout) {
   const int nch = (bi + 1 + kChunk - 1) / kChunk;
   __syncthreads();  // B0
   for (int r = lane; r < nt * kTile; r += NTHR) sm.gv[r] = T(0);
@@ -729,10 +731,10 @@ __device__ __forceinline__ void panel_adjoint(SM& sm, int lane, int nt, int mi, 
       __syncthreads();  // B2
       __syncthreads();  // B3
     }
-    rhs_writeback<T, NTHR>(sm, lane, ch, mi, nA, bi, gout);
+    rhs_writeback<T, NTHR>(sm, lane, ch, mi, nA, bi, ld, gout);
     __syncthreads();  // B4
   }
-  for (int r = lane; r < nA; r += NTHR) gout[nA + r] = sm.gv[r];
+  for (int r = lane; r < nA; r += NTHR) gout[ld + r] = sm.gv[r];
 }
 
 // PRE: large-block mode.  The block's first p = ceil(nA/16) - NTM tile rows
@@ -745,7 +747,7 @@ __global__ __launch_bounds__(NW * 64) void k_block_loglik(const SetDesc* __restr
                                                           const WorkItem* __restrict__ items,
                                                           const int* __restrict__ count,
                                                           double piv_tau, LargeArgs L) {
-  static_assert(!PRE || (!GRAD && !SAMPLE && !LA && NTM == kLargeNTM), "large-block mode is forward only");
+  static_assert(!PRE || (!SAMPLE && !LA && NTM == kLargeNTM), "large-block mode: no simulation, no lookahead");
   __shared__ Smem<T, NTM, GRAD> sm;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -778,7 +780,7 @@ __global__ __launch_bounds__(NW * 64) void k_block_loglik(const SetDesc* __restr
     const int nt = (nAl + kTile - 1) / kTile;
     const T sigma2 = T(exp(th[d]));
     const T tau2 = T(exp(th[d + 1]));
-    T* gout = GRAD ? reinterpret_cast<T*>(S.qbuf) + S.qoff[w.block] : nullptr;
+    T* gout = GRAD ? reinterpret_cast<T*>(S.qbuf) + S.qoff[w.block] + off : nullptr;
     const T* Wp = PRE ? reinterpret_cast<const T*>(L.W) + (int64_t)it * kLargeW : nullptr;
     const T* zp = PRE ? reinterpret_cast<const T*>(L.z) + (int64_t)it * kLargeZ : nullptr;
 
@@ -824,13 +826,13 @@ __global__ __launch_bounds__(NW * 64) void k_block_loglik(const SetDesc* __restr
         S.llb[w.block] = l;
         S.flag[w.block] = PRE ? (S.flag[w.block] | fb) : fb;  // PRE: keep the prefix kernel's flags
       }
-      if (GRAD) panel_adjoint<T, NW * 64>(sm, lane, nt, mi, nA, bi, gout);
+      if (GRAD) panel_adjoint<T, NW * 64>(sm, lane, nt, mil, nAl, bi, nA, gout);
     } else {
       if (LA)
         worker_waves_la<T, NTM, NW - 1, NW * 64>(sm, wave - 1, lane, nt, nA, d, S.two_nu, sigma2, tau2);
       else
         worker_waves<T, NTM, NW - 1, NW * 64, GRAD, PRE>(sm, wave - 1, lane, nt, mil, nAl, bi, d, S.two_nu,
-                                                         sigma2, tau2, gout, pre, Wp, zp);
+                                                         sigma2, tau2, gout, nA, pre, Wp, zp);
     }
     __syncthreads();
   }
@@ -929,7 +931,7 @@ __device__ __forceinline__ void prefix_panel_wave(SM& sm, int lane, int p, int c
 template <typename T, int NTM, int NWK, int NTHR, class SM>
 __device__ __forceinline__ void prefix_worker_waves(SM& sm, int wk, int lane, int p, int c, const SetDesc& S,
                                                     int b0, int64_t n0, int mi, int nA, int d, const double* th,
-                                                    T sigma2, T tau2, T* Wout) {
+                                                    T sigma2, T tau2, T* Wout, T* Lout) {
   typedef typename MF<T>::acc acc_t;
   constexpr int NTT = NTM * (NTM + 1) / 2;
   constexpr int SLOTS = (NTT + NWK - 1) / NWK;
@@ -1022,6 +1024,13 @@ __device__ __forceinline__ void prefix_worker_waves(SM& sm, int wk, int lane, in
         const T* src = sm.panel + 256 * p;
         for (int e = tid - 64; e < cc * 256; e += NTHR - 64) dst[e] = src[e];
       }
+      // for the adjoint: column k of L_PP (tile (j, k) at slot k * kMaxPrefix + j,
+      // operand layout) and -L_kk^{-T} in the diagonal slot
+      if (Lout && ch == 0) {
+        T* dst = Lout + (int64_t)k * kMaxPrefix * 256;
+        for (int e = 256 * k + tid - 64; e < p * 256; e += NTHR - 64)
+          dst[e] = e < 256 * (k + 1) ? sm.negMs[e] : sm.panel[e];
+      }
       // trailing update restricted to columns of P (the R x R part is left to
       // the register kernel)
 #pragma unroll
@@ -1066,6 +1075,7 @@ __global__ __launch_bounds__(NW * 64) void k_block_prefix(const SetDesc* __restr
     const T tau2 = T(exp(th[d + 1]));
     T* Wout = reinterpret_cast<T*>(L.W) + (int64_t)it * kLargeW;
     T* zout = reinterpret_cast<T*>(L.z) + (int64_t)it * kLargeZ;
+    T* Lout = L.Lpp ? reinterpret_cast<T*>(L.Lpp) + (int64_t)it * kLargeL : nullptr;
     gather_points<T, NW * 64>(sm.z, sm.yv, tid, 0, kTile * p, 0, d, mi, nA, S, b0, n0, th);
     __syncthreads();
     if (wave == 0) {
@@ -1075,7 +1085,7 @@ __global__ __launch_bounds__(NW * 64) void k_block_prefix(const SetDesc* __restr
       if (lane == 0) S.flag[w.block] = (bad ? 2 : 0) | (low ? 1 : 0);
     } else {
       prefix_worker_waves<T, kLargeNTM, NW - 1, NW * 64>(sm, wave - 1, lane, p, c, S, b0, n0, mi, nA, d, th,
-                                                         sigma2, tau2, Wout);
+                                                         sigma2, tau2, Wout, Lout);
     }
     __syncthreads();
   }
@@ -1236,6 +1246,205 @@ __global__ __launch_bounds__(NW * 64) void k_block_contract(const SetDesc* __res
   }
 }
 
+// ---- large blocks: prefix part of the adjoint ---------------------------------
+// With L = [L_PP, 0; L_RP, L_T] the adjoint solves L^T X = Rhs split into
+//   L_T^T X_R = Rhs_R                       (the trailing kernel, GRAD mode),
+//   L_PP^T X_P = Rhs_P - L_RP^T X_R,
+// for the columns e (Rhs_P = z_P), g and those of Q (Rhs_P = 0).  This kernel
+// forms the second right-hand side 32 columns at a time and solves it
+// backwards with the stored L_PP tiles and inverted diagonal tiles; X_P goes to
+// rows 0..16p-1 of the block's adjoint buffer, which then holds e, g and Q
+// over the whole joint set.
+template <typename T>
+struct SmemPA {
+  T xr[kLargeNTM * kTile * kRS];   // chunk of X_R (rows of R)
+  T rp[kMaxPrefix * kTile * kRS];  // right-hand side, then solution, of the prefix rows
+  T xk[kTile * kRS];               // solved tile row k
+};
+
+template <typename T, int NW>
+__global__ __launch_bounds__(NW * 64) void k_block_prefix_adjoint(const SetDesc* __restrict__ sets,
+                                                                  const WorkItem* __restrict__ items,
+                                                                  const int* __restrict__ count, LargeArgs L) {
+  constexpr int NTHR = NW * 64;
+  __shared__ SmemPA<T> sm;
+  const int tid = threadIdx.x;
+  const int total = min(max(*count - L.off, 0), L.nb);
+  for (int it = blockIdx.x; it < total; it += gridDim.x) {
+    const WorkItem w = items[L.off + it];
+    const SetDesc S = sets[w.set];
+    const int b0 = S.bptr[w.block], b1 = S.bptr[w.block + 1];
+    const int64_t n0 = S.nptr[w.block], n1 = S.nptr[w.block + 1];
+    const int mi = (int)(n1 - n0), bi = b1 - b0, nA = mi + bi;
+    const int p = (nA + kTile - 1) / kTile - kLargeNTM;
+    if (p < 1 || p > kMaxPrefix || kTile * p > mi) continue;  // never queued by the host
+    const int np = kTile * p, nR = nA - np;
+    T* qb = reinterpret_cast<T*>(S.qbuf) + S.qoff[w.block];
+    const T* Wp = reinterpret_cast<const T*>(L.W) + (int64_t)it * kLargeW;
+    const T* Lp = reinterpret_cast<const T*>(L.Lpp) + (int64_t)it * kLargeL;
+    const T* zp = reinterpret_cast<const T*>(L.z) + (int64_t)it * kLargeZ;
+    const int ncol = bi + 2;  // e, g, then the columns of Q (column c at c * nA)
+    for (int c0 = 0; c0 < ncol; c0 += kChunk) {
+      for (int e = tid; e < nR * kChunk; e += NTHR) {
+        const int r = e / kChunk, c = e - r * kChunk;
+        sm.xr[r * kRS + c] = c0 + c < ncol ? qb[(int64_t)(c0 + c) * nA + np + r] : T(0);
+      }
+      __syncthreads();
+      // Rhs_P - L_RP^T X_R; workspace tile (k, i) holds L[16p + 16i + a][16k + b] at opoff(a, b)
+      for (int e = tid; e < np * kChunk; e += NTHR) {
+        const int rr = e / kChunk, c = e - rr * kChunk;
+        const T* Wk = Wp + (int64_t)(rr >> 4) * kLargeNTM * 256;
+        const int cc = rr & 15;
+        T acc = T(0);
+        for (int r = 0; r < nR; ++r) acc += Wk[(r >> 4) * 256 + opoff<T>(r & 15, cc)] * sm.xr[r * kRS + c];
+        sm.rp[rr * kRS + c] = (c0 + c == 0 ? zp[rr] : T(0)) - acc;
+      }
+      __syncthreads();
+      for (int k = p - 1; k >= 0; --k) {
+        // X_k = L_kk^{-T} Rhs_k; the diagonal slot holds -(L_kk^{-1})[a][b] at opoff(a, b)
+        const T* nM = Lp + ((int64_t)k * kMaxPrefix + k) * 256;
+        for (int e = tid; e < kTile * kChunk; e += NTHR) {
+          const int a = e / kChunk, c = e - a * kChunk;
+          T acc = T(0);
+          for (int b = 0; b < kTile; ++b) acc -= nM[opoff<T>(b, a)] * sm.rp[(kTile * k + b) * kRS + c];
+          sm.xk[a * kRS + c] = acc;
+        }
+        __syncthreads();
+        for (int e = tid; e < kTile * kChunk; e += NTHR) {
+          const int a = e / kChunk, c = e - a * kChunk;
+          sm.rp[(kTile * k + a) * kRS + c] = sm.xk[a * kRS + c];
+        }
+        // Rhs_j -= L_kj^T X_k for j < k; tile (k, j) sits in slot j * kMaxPrefix + k
+        for (int e = tid; e < kTile * k * kChunk; e += NTHR) {
+          const int rr = e / kChunk, c = e - rr * kChunk;
+          const T* Lkj = Lp + ((int64_t)(rr >> 4) * kMaxPrefix + k) * 256;
+          const int b = rr & 15;
+          T acc = T(0);
+          for (int a = 0; a < kTile; ++a) acc += Lkj[opoff<T>(a, b)] * sm.xk[a * kRS + c];
+          sm.rp[rr * kRS + c] -= acc;
+        }
+        __syncthreads();
+      }
+      for (int e = tid; e < np * kChunk; e += NTHR) {
+        const int rr = e / kChunk, c = e - rr * kChunk;
+        if (c0 + c < ncol) qb[(int64_t)(c0 + c) * nA + rr] = sm.rp[rr * kRS + c];
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// ---- large blocks: streamed gradient contraction -----------------------------
+// The same contraction as k_block_contract over the whole joint set, with the
+// tiles of the lower triangle taken one at a time by the waves (Q Q^T of a
+// tile on MFMA, operands read from the adjoint buffer) instead of held in
+// registers.
+template <typename T>
+struct SmemCS {
+  T z[(kLargeNTM + kMaxPrefix) * kTile * kMaxDim];
+  T ev[(kLargeNTM + kMaxPrefix) * kTile];
+  T gv[(kLargeNTM + kMaxPrefix) * kTile];
+  double red[8][kMaxDim + 2];
+};
+
+template <typename T, int NW>
+__global__ __launch_bounds__(NW * 64) void k_block_contract_stream(const SetDesc* __restrict__ sets,
+                                                                   const double* __restrict__ theta,
+                                                                   const WorkItem* __restrict__ items,
+                                                                   const int* __restrict__ count, LargeArgs L) {
+  static_assert(NW <= 8, "reduction buffer holds 8 waves");
+  typedef typename MF<T>::acc acc_t;
+  constexpr int NTHR = NW * 64;
+  __shared__ SmemCS<T> sm;
+  const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int g = lane >> 4, cl = lane & 15;
+  const int total = min(max(*count - L.off, 0), L.nb);
+  for (int it = blockIdx.x; it < total; it += gridDim.x) {
+    const WorkItem w = items[L.off + it];
+    const SetDesc S = sets[w.set];
+    const int d = S.d, two_nu = S.two_nu;
+    const double* th = theta + S.theta_off;
+    const int b0 = S.bptr[w.block], b1 = S.bptr[w.block + 1];
+    const int64_t n0 = S.nptr[w.block], n1 = S.nptr[w.block + 1];
+    const int mi = (int)(n1 - n0), bi = b1 - b0, nA = mi + bi;
+    const int nt = (nA + kTile - 1) / kTile;
+    if (nt > kLargeNTM + kMaxPrefix) continue;  // never queued by the host
+    const int ntt = nt * (nt + 1) / 2;
+    const T sigma2 = T(exp(th[d]));
+    const T tau2 = T(exp(th[d + 1]));
+    const T* src = reinterpret_cast<const T*>(S.qbuf) + S.qoff[w.block];
+    for (int e = tid; e < nA * d; e += NTHR) {
+      const int pa = e / d, k = e - pa * d;
+      const int pos = pa < mi ? S.nidx[n0 + pa] : b0 + (pa - mi);
+      sm.z[pa * d + k] = T(S.X[(int64_t)pos * d + k] * exp(-th[k]));
+    }
+    for (int r = tid; r < nt * kTile; r += NTHR) {
+      sm.ev[r] = r < nA ? src[r] : T(0);
+      sm.gv[r] = r < nA ? src[nA + r] : T(0);
+    }
+    __syncthreads();
+    double gacc[kMaxDim + 2];
+#pragma unroll
+    for (int k = 0; k < kMaxDim + 2; ++k) gacc[k] = 0.0;
+    for (int t = wave; t < ntt; t += NW) {
+      int i, j = 0, tt = t;
+      while (tt >= nt - j) {
+        tt -= nt - j;
+        ++j;
+      }
+      i = j + tt;
+      const int ra = kTile * i + cl, rb = kTile * j + cl;
+      acc_t P = {T(0), T(0), T(0), T(0)};
+      for (int q0 = 0; q0 < bi; q0 += 4) {
+        const int c = q0 + g;
+        const T qa = (c < bi && ra < nA) ? src[(int64_t)(2 + c) * nA + ra] : T(0);
+        const T qc = (c < bi && rb < nA) ? src[(int64_t)(2 + c) * nA + rb] : T(0);
+        P = MF<T>::mma(qa, qc, P);
+      }
+      const double wgt = i == j ? 1.0 : 2.0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int a = kTile * i + MF<T>::row(g, q);
+        const int b = kTile * j + cl;
+        if (a >= nA || b >= nA) continue;
+        const T M = sm.ev[a] * sm.gv[b] + sm.gv[a] * sm.ev[b] + sm.gv[a] * sm.gv[b] - P[q];
+        T r2 = T(0);
+        for (int k = 0; k < d; ++k) {
+          const T df = sm.z[a * d + k] - sm.z[b * d + k];
+          r2 += df * df;
+        }
+        const T r = t_sqrt(r2);
+        const double wm = wgt * (double)M;
+        const double f = wm * (double)(sigma2 * mdrho_over_r<T>(r, two_nu));
+#pragma unroll
+        for (int k = 0; k < kMaxDim; ++k) {
+          if (k < d) {
+            const T df = sm.z[a * d + k] - sm.z[b * d + k];
+            gacc[k] += f * (double)(df * df);
+          }
+        }
+        gacc[kMaxDim] += wm * (double)(sigma2 * matern<T>(r, two_nu));
+        if (a == b) gacc[kMaxDim + 1] += wm * (double)tau2;
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < kMaxDim + 2; ++k) {
+      double v = gacc[k];
+#pragma unroll
+      for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+      if (lane == 0) sm.red[wave][k] = v;
+    }
+    __syncthreads();
+    if (tid < d + 2) {
+      const int k = tid < d ? tid : kMaxDim + (tid - d);
+      double v = 0.0;
+      for (int wv = 0; wv < NW; ++wv) v += sm.red[wv][k];
+      S.gradb[(int64_t)w.block * (d + 2) + tid] = 0.5 * v;
+    }
+    __syncthreads();
+  }
+}
+
 // ---- variants -------------------------------------------------------------
 static const Variant kVariants[] = {{4, 2}, {8, 4}, {12, 8}, {14, 8}, {16, 8}, {17, 8}};
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
@@ -1318,6 +1527,29 @@ hipError_t launch_large(int prec, int grid, const SetDesc* sets, const double* t
   if (grid <= 0) return hipSuccess;
   if (prec == 0) return launch_large_t<double>(grid, sets, theta, items, count, piv_tau, L, s);
   return launch_large_t<float>(grid, sets, theta, items, count, piv_tau, L, s);
+}
+
+template <typename T>
+static hipError_t launch_large_grad_t(int grid, const SetDesc* sets, const double* theta, const WorkItem* items,
+                                      const int* count, double piv_tau, const LargeArgs& L, hipStream_t s) {
+  if (!L.Lpp) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_block_prefix<T, 8>), dim3(grid), dim3(512), 0, s, sets, theta, items, count, piv_tau, L);
+  hipError_t e = hipGetLastError();
+  if (e) return e;
+  hipLaunchKernelGGL((k_block_loglik<T, kLargeNTM, 8, true, false, false, true>), dim3(grid), dim3(512), 0, s,
+                     sets, theta, items, count, piv_tau, L);
+  if ((e = hipGetLastError())) return e;
+  hipLaunchKernelGGL((k_block_prefix_adjoint<T, 8>), dim3(grid), dim3(512), 0, s, sets, items, count, L);
+  if ((e = hipGetLastError())) return e;
+  hipLaunchKernelGGL((k_block_contract_stream<T, 8>), dim3(grid), dim3(512), 0, s, sets, theta, items, count, L);
+  return hipGetLastError();
+}
+
+hipError_t launch_large_grad(int prec, int grid, const SetDesc* sets, const double* theta, const WorkItem* items,
+                             const int* count, double piv_tau, const LargeArgs& L, hipStream_t s) {
+  if (grid <= 0) return hipSuccess;
+  if (prec == 0) return launch_large_grad_t<double>(grid, sets, theta, items, count, piv_tau, L, s);
+  return launch_large_grad_t<float>(grid, sets, theta, items, count, piv_tau, L, s);
 }
 
 hipError_t launch_sample(int v, int grid, const SetDesc* sets, const double* theta, const WorkItem* items,

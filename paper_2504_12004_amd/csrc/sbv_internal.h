@@ -55,15 +55,19 @@ constexpr int kLargeNTM = 17;
 constexpr int kMaxPrefix = 15;  // joint sizes up to 16 * (kLargeNTM + kMaxPrefix) = 512
 constexpr int64_t kLargeW = (int64_t)kMaxPrefix * kLargeNTM * 256;  // panel elements per workspace slot
 constexpr int64_t kLargeZ = (int64_t)kMaxPrefix * kTile;            // z elements per workspace slot
+constexpr int64_t kLargeL = (int64_t)kMaxPrefix * kMaxPrefix * 256;  // L_PP elements per slot (gradient)
 
 // Workspace window of one launch of the large-block kernels: they process
 // items[off + i] for i < min(*count - off, nb), item i using workspace slot i
-// (W + i * kLargeW, z + i * kLargeZ, elements of the kernel precision).
+// (W + i * kLargeW, z + i * kLargeZ, Lpp + i * kLargeL, elements of the kernel
+// precision).  Lpp (the prefix factor, kept for the adjoint) may be null on
+// the forward path.
 struct LargeArgs {
   int32_t off;
   int32_t nb;
   void* W;
   void* z;
+  void* Lpp;
 };
 
 // Prefix length p of a block with joint size nA and m_i conditioning points
@@ -98,6 +102,11 @@ int max_grid(int prec, int variant);
 // Both kernels of the large path for one workspace window (prec 0 FP64, 1 FP32).
 hipError_t launch_large(int prec, int grid, const SetDesc* sets, const double* theta, const WorkItem* items,
                         const int* count, double piv_tau, const LargeArgs& L, hipStream_t s);
+// Large path with the gradient: prefix kernel (keeping L_PP), trailing factor
+// with its adjoint solves, the prefix part of the adjoint, and the streamed
+// contraction; per-block gradients land in gradb.  L.Lpp must be set.
+hipError_t launch_large_grad(int prec, int grid, const SetDesc* sets, const double* theta, const WorkItem* items,
+                             const int* count, double piv_tau, const LargeArgs& L, hipStream_t s);
 
 }  // namespace sbv
 

@@ -75,10 +75,10 @@ def test_fp64_prefix_extremes(sbv):
 
 
 def test_fp32_large(sbv):
-    # tau2 = 1e-3: at n = 4000 the total is a sum of terms of both signs (|l|
-    # is about 500), so the relative bound is tight; the structure still has
-    # joint sizes up to 460
-    X, y, th, S = problem(4000, 10, K=200, m=400, seed=33, tau2=1e-3, min_bs=5, max_bs=60, m_gen=60)
+    # sigma^2 = 4: with sigma^2 = 1 the per-point terms of this small dataset
+    # take both signs and the total (|l| ~ 100-500) is mostly cancellation, which
+    # makes a relative bound on it meaningless; here |l| ~ 3400
+    X, y, th, S = problem(4000, 10, K=200, m=400, seed=33, sigma2=4.0, tau2=1e-4, min_bs=5, max_bs=60, m_gen=60)
     B = _compare(sbv, X, y, th, S, 5, sbv.SBV_FP32, 1e-4)
     B.free()
 
@@ -105,9 +105,46 @@ def test_large_rejections(sbv):
     X, y, th, S = _explicit(600, 3, sizes, targets, seed=35)
     with pytest.raises(sbv.SBVError):
         to_gpu(sbv, X, y, S)
-    # gradient and simulator stay within the register path
-    X, y, th, S = problem(2000, 10, K=100, m=400, seed=36, tau2=1e-4, min_bs=5, max_bs=60, m_gen=60)
+    # the conditional simulator stays within the register path
+    X, y, th, S = problem(1500, 5, K=60, m=300, seed=36, tau2=1e-3, m_gen=40)
     B = to_gpu(sbv, X, y, S)
     with pytest.raises(sbv.SBVError):
-        sbv.sbv_loglik_grad(B, th, 5)
+        sbv.sbv_sample(B, th, 5, np.zeros(X.shape[0]))
+    B.free()
+
+
+def _grad_cmp(sbv, X, y, th, S, two_nu, prec, tol):
+    ref_l, ref_g = O.sbv_loglik(X, y, S, th, two_nu, grad=True)
+    B = to_gpu(sbv, X, y, S)
+    l, g = sbv.sbv_loglik_grad(B, th, two_nu, prec)
+    scale = max(1.0, np.max(np.abs(ref_g)))
+    err = np.max(np.abs(g - ref_g)) / scale
+    print(f"l {l[0]!r} ref {ref_l!r}; grad max rel err {err:.3e}", flush=True)
+    assert abs(l[0] - ref_l) <= 1e-10 * abs(ref_l)
+    assert err <= tol
+    return B
+
+
+def test_grad_large_fp64(sbv):
+    # every component of the gradient through the prefix adjoint and the
+    # streamed contraction, blocks of up to 60 points (two right-hand-side chunks)
+    X, y, th, S = problem(2000, 10, K=100, m=400, seed=37, tau2=1e-4, min_bs=5, max_bs=60, m_gen=60)
+    joint = np.diff(S.nn_ptr) + np.diff(S.block_ptr)
+    assert (joint > 272).sum() > 30 and np.diff(S.block_ptr).max() > 32
+    B = _grad_cmp(sbv, X, y, th, S, 5, sbv.SBV_FP64, 1e-8)
+    B.free()
+
+
+def test_grad_large_extremes_and_fallback(sbv, monkeypatch):
+    sizes = [32] * 24 + [60, 32, 17, 32, 5, 32]
+    targets = [0] * 8 + [241, 480, 452, 300, 256, 257, 399, 400, 480, 272, 240, 16] + [0] * 4 + \
+              [452, 241, 470, 480, 507, 400]
+    X, y, th, S = _explicit(int(np.sum(sizes)), 5, sizes, targets, seed=38)
+    monkeypatch.setenv("SBV_LARGE_WINDOW", "5")
+    B = _grad_cmp(sbv, X, y, th, S, 3, sbv.SBV_FP64, 1e-8)
+    B.free()
+    # FP32 with every block sent back to FP64: the FP64 bar applies
+    monkeypatch.setenv("SBV_PIV_TAU", "2.0")
+    B = _grad_cmp(sbv, X, y, th, S, 3, sbv.SBV_FP32, 1e-8)
+    assert sbv.sbv_blocks_fallback_count(B) == S.K
     B.free()
