@@ -497,7 +497,13 @@ sbv_status sbv_fit(sbv_blocks set, const double* theta0, int32_t two_nu, const s
   Objective obj{fit_objective, &c};
   double fb = INFINITY;
   bool conv = false;
-  sbv_status st = run_minimize(o->optimizer, x, obj, *o, fb, conv);
+  // With an FP64 polish to follow, the FP32 phase stops once an iteration
+  // changes -l by less than kFp32Ftol relative: below that, FP32 rounding of
+  // the block terms hides real progress and line searches only fail.
+  constexpr double kFp32Ftol = 1e-7;
+  sbv_fit_opts first = *o;
+  if (o->fp64_polish && o->prec == SBV_FP32) first.ftol = std::max(o->ftol, kFp32Ftol);
+  sbv_status st = run_minimize(o->optimizer, x, obj, first, fb, conv);
   if (st) return st;
   if (c.last != SBV_OK) return c.last;
   int64_t evals = obj.evals;

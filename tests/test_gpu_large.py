@@ -148,3 +148,17 @@ def test_grad_large_extremes_and_fallback(sbv, monkeypatch):
     B = _grad_cmp(sbv, X, y, th, S, 3, sbv.SBV_FP32, 1e-8)
     assert sbv.sbv_blocks_fallback_count(B) == S.K
     B.free()
+
+
+def test_grad_m400_workload_subset(sbv):
+    # the generator of the n = 5e6, m = 400 workload at n = 2e4 with its own
+    # structure (K = 1000, k-means blocks of 5..60 points, m = 400)
+    w = synth.dataset("grad_5m", n=20000)
+    X, th, xi = w["X"], w["theta"], w["xi"]
+    bb = np.exp(th[:10])
+    Sg = O.build(X, bb, K=1000, m=100, lloyd_iters=1, seed=w["seed"] + 7919)
+    y = O.sample(X, Sg, th, 5, xi)
+    S = O.build(X, bb, K=1000, m=400, lloyd_iters=5, min_bs=5, max_bs=60, seed=w["seed"])
+    assert (np.diff(S.nn_ptr) + np.diff(S.block_ptr)).max() > 400
+    B = _grad_cmp(sbv, X, y, th, S, 5, sbv.SBV_FP64, 1e-8)
+    B.free()
