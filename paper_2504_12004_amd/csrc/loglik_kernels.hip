@@ -119,15 +119,21 @@ __device__ unsigned long long g_phase[16];
 constexpr int kRS = 33;
 constexpr int kChunk = 32;
 
+// FP64 register kernels generate covariance columns late (interleaved with the
+// factorisation, see worker_waves); FP32 ones generate them all first.
+template <typename T>
+constexpr bool kLateCov = sizeof(T) == 8;
+
 template <typename T, int NTM, bool GRAD = false>
 struct Smem {
   static constexpr int kPanel = NTM * 256;
   static constexpr int kRhs = NTM * kTile * kRS;
   T z[NTM * kTile * kMaxDim];  // scaled coordinates of A (padded rows unused)
   T yv[NTM * kTile];           // observations, overwritten by the forward solve
-  // column k of L in operand layout (factorisation) / right-hand-side chunk
-  // (adjoint solves, GRAD only)
-  T panel[(GRAD && kRhs > kPanel) ? kRhs : kPanel];
+  // column k of L in operand layout (factorisation); its second half stages
+  // the next covariance column; right-hand-side chunk of the adjoint solves
+  // (GRAD only)
+  T panel[(GRAD && kRhs > 2 * kPanel) ? kRhs : 2 * kPanel];
   T diag[256];                 // diagonal tile to factor (row-major)
   T negM[256];                 // -(L_kk^{-T}) in B-operand layout
   T zk[kTile];                 // solved z of the current tile row
@@ -152,6 +158,52 @@ __device__ __forceinline__ float rsqrt_nr(float p) {
 
 __device__ __forceinline__ double shfl_d(double v, int src) { return __shfl(v, src, 64); }
 __device__ __forceinline__ float shfl_d(float v, int src) { return __shfl(v, src, 64); }
+
+// Lane j of every 16-lane row broadcast to its row (DPP row_newbcast, j a
+// constant after unrolling), and row gj broadcast to all four rows
+// (v_permlane16_swap then v_permlane32_swap).  Both checked on the device.
+template <int J>
+__device__ __forceinline__ unsigned nb_u(unsigned v) {
+  return (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x150 + J, 0xf, 0xf, false);
+}
+__device__ __forceinline__ unsigned row_lane_u(unsigned v, int j) {
+  switch (j) {
+    case 0: return nb_u<0>(v);
+    case 1: return nb_u<1>(v);
+    case 2: return nb_u<2>(v);
+    case 3: return nb_u<3>(v);
+    case 4: return nb_u<4>(v);
+    case 5: return nb_u<5>(v);
+    case 6: return nb_u<6>(v);
+    case 7: return nb_u<7>(v);
+    case 8: return nb_u<8>(v);
+    case 9: return nb_u<9>(v);
+    case 10: return nb_u<10>(v);
+    case 11: return nb_u<11>(v);
+    case 12: return nb_u<12>(v);
+    case 13: return nb_u<13>(v);
+    case 14: return nb_u<14>(v);
+    default: return nb_u<15>(v);
+  }
+}
+__device__ __forceinline__ unsigned row_all_u(unsigned x, int gj) {
+  const auto a = __builtin_amdgcn_permlane16_swap(x, x, false, false);  // rows (0 0 2 2) / (1 1 3 3)
+  const unsigned e = (gj & 1) ? a[1] : a[0];
+  const auto b = __builtin_amdgcn_permlane32_swap(e, e, false, false);   // lower / upper half doubled
+  return (gj & 2) ? b[1] : b[0];
+}
+__device__ __forceinline__ double row_lane(double v, int j) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = row_lane_u((unsigned)u, j), hi = row_lane_u((unsigned)(u >> 32), j);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+__device__ __forceinline__ float row_lane(float v, int j) { return __uint_as_float(row_lane_u(__float_as_uint(v), j)); }
+__device__ __forceinline__ double row_all(double v, int gj) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = row_all_u((unsigned)u, gj), hi = row_all_u((unsigned)(u >> 32), gj);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+__device__ __forceinline__ float row_all(float v, int gj) { return __uint_as_float(row_all_u(__float_as_uint(v), gj)); }
 
 // Factor the 16x16 SPD tile in sm.diag on one wave with all 64 lanes: lane
 // (r, g) = (l % 16, l / 16) holds columns c = g + 4q (q = 0..3) of row r.
@@ -185,10 +237,10 @@ __device__ __forceinline__ void factor_diag(SM& sm, T* negM_out, int lane, int k
     const T rs = rsqrt_nr(piv);
     const T sq = piv * rs;
     // A[r][j] of my row and row j of my columns, before this step's update
-    const T arj = shfl_d(a[qj], r + 16 * gj);
+    const T arj = row_all(a[qj], gj);
     T ajc[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) ajc[q] = shfl_d(a[q], j + 16 * g);
+    for (int q = 0; q < 4; ++q) ajc[q] = row_lane(a[q], j);
     const T lrj = (r == j) ? sq : arj * rs;  // L[r][j] (r >= j)
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -201,7 +253,7 @@ __device__ __forceinline__ void factor_diag(SM& sm, T* negM_out, int lane, int k
     for (int q = 0; q < 4; ++q) x[q] = (r == j) ? x[q] * rs : x[q];
     T xjc[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) xjc[q] = shfl_d(x[q], j + 16 * g);
+    for (int q = 0; q < 4; ++q) xjc[q] = row_lane(x[q], j);
 #pragma unroll
     for (int q = 0; q < 4; ++q) x[q] = (r > j) ? x[q] - lrj * xjc[q] : x[q];
     T zj;
@@ -234,8 +286,8 @@ __device__ __forceinline__ void factor_diag(SM& sm, T* negM_out, int lane, int k
 }
 
 template <typename T, int NTHR, class SM>
-__device__ __forceinline__ void gen_column(SM& sm, int tid, int j, int i0, int nt, int nA, int d, int two_nu,
-                                           T sigma2, T tau2) {
+__device__ __forceinline__ void gen_column(SM& sm, T* dst, int tid, int j, int i0, int nt, int nA, int d,
+                                           int two_nu, T sigma2, T tau2) {
   // tiles (i, j) for i = i0..nt-1.  One work item = (tile i, lane l): the 4
   // entries of accumulator registers t = 0..3, which share the point
   // 16i + l%16 (read once) and differ in the point 16j + row(l/16, t)
@@ -272,7 +324,7 @@ __device__ __forceinline__ void gen_column(SM& sm, int tid, int j, int i0, int n
         v = -(sigma2 * matern<T>(t_sqrt(r2[t]), two_nu));
         if (pa[t] == pb) v -= tau2;
       }
-      sm.panel[256 * i + 64 * t + l] = v;
+      dst[256 * i + 64 * t + l] = v;
     }
   }
 }
@@ -328,10 +380,12 @@ __device__ __forceinline__ void panel_wave(SM& sm, int lane, int nt, int mi, int
                                            double* yout, int p, const T* Wp, const T* zp) {
   const T diag0 = sigma2 + tau2;
   SBV_PROF_DECL
-  for (int j = 0; j < nt; ++j) {
-    gen_column<T, NTHR>(sm, lane, j, j, nt, nA, d, two_nu, sigma2, tau2);
-    __syncthreads();  // G1
-    __syncthreads();  // G2
+  if (!kLateCov<T>) {
+    for (int j = 0; j < nt; ++j) {
+      gen_column<T, NTHR>(sm, sm.panel, lane, j, j, nt, nA, d, two_nu, sigma2, tau2);
+      __syncthreads();  // G1
+      __syncthreads();  // G2
+    }
   }
   if (PRE) {
     // large block: y -= L_RP z_P, one prefix column tile at a time
@@ -342,6 +396,7 @@ __device__ __forceinline__ void panel_wave(SM& sm, int lane, int nt, int mi, int
       __syncthreads();  // P2: staging area free
     }
   }
+  if (kLateCov<T>) __syncthreads();  // G0: covariance column 0 staged (by the workers)
   SBV_PROF(0, true);
   for (int k = 0; k < nt; ++k) {
     __syncthreads();  // S1: diagonal tile published
@@ -390,10 +445,15 @@ template <typename T, int NTM, int NTHR, class SM>
 __device__ __forceinline__ void panel_wave_la(SM& sm, int lane, int nt, int mi, int nA, int d, int two_nu, T sigma2, T tau2, T tau,
                               double& ld_acc, double& q_acc, int& bad, int& low) {
   const T diag0 = sigma2 + tau2;
-  for (int j = 0; j < nt; ++j) {
-    gen_column<T, NTHR>(sm, lane, j, j, nt, nA, d, two_nu, sigma2, tau2);
-    __syncthreads();  // G1
-    __syncthreads();  // G2
+  if (kLateCov<T>) {
+    __syncthreads();  // Ga: covariance column 0 staged
+    __syncthreads();  // Gb: column 0 added, diagonal tile 0 published
+  } else {
+    for (int j = 0; j < nt; ++j) {
+      gen_column<T, NTHR>(sm, sm.panel, lane, j, j, nt, nA, d, two_nu, sigma2, tau2);
+      __syncthreads();  // G1
+      __syncthreads();  // G2
+    }
   }
   auto factor_step = [&](int k) {
     while (__atomic_load_n(&sm.la_flag, __ATOMIC_ACQUIRE) < k) __builtin_amdgcn_s_sleep(1);
@@ -448,19 +508,43 @@ __device__ __forceinline__ void worker_waves_la(SM& sm, int wk, int lane, int nt
 #pragma unroll
     for (int t = 0; t < 4; ++t) acc[s][t] = T(0);
   }
-  for (int j = 0; j < nt; ++j) {
-    refresh_slots<SLOTS>(ti, tj);
-    gen_column<T, NTHR>(sm, 64 * (wk + 1) + lane, j, j, nt, nA, d, two_nu, sigma2, tau2);
-    __syncthreads();  // G1
+  // FP64: covariance column j is staged by the workers during step j-2 (after
+  // their updates, while the panel wave factors) and added by its owners at
+  // the start of step j-1, before that step's update and early publication
+  // of the diagonal tile j; columns 0 and 1 are staged up front.  FP32
+  // generates every column first (see worker_waves).
+  T* stage = sm.panel + Smem<T, NTM, false>::kPanel;
+  const int wtid = 64 * wk + lane;
+  auto add_staged = [&](int j) {
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
       if (tj[s] == j) {
-        const T* src = sm.panel + 256 * ti[s];
+        const T* src = stage + 256 * ti[s];
 #pragma unroll
-        for (int t = 0; t < 4; ++t) acc[s][t] = src[64 * t + lane];
+        for (int t = 0; t < 4; ++t) acc[s][t] += src[64 * t + lane];
       }
     }
-    __syncthreads();  // G2
+  };
+  if (kLateCov<T>) {
+    gen_column<T, NTHR - 64>(sm, stage, wtid, 0, 0, nt, nA, d, two_nu, sigma2, tau2);
+    __syncthreads();  // Ga
+    refresh_slots<SLOTS>(ti, tj);
+    add_staged(0);
+  } else {
+    for (int j = 0; j < nt; ++j) {
+      refresh_slots<SLOTS>(ti, tj);
+      gen_column<T, NTHR>(sm, sm.panel, 64 * (wk + 1) + lane, j, j, nt, nA, d, two_nu, sigma2, tau2);
+      __syncthreads();  // G1
+#pragma unroll
+      for (int s = 0; s < SLOTS; ++s) {
+        if (tj[s] == j) {
+          const T* src = sm.panel + 256 * ti[s];
+#pragma unroll
+          for (int t = 0; t < 4; ++t) acc[s][t] = src[64 * t + lane];
+        }
+      }
+      __syncthreads();  // G2
+    }
   }
   auto publish_diag = [&](int s, int k) {
 #pragma unroll
@@ -472,9 +556,14 @@ __device__ __forceinline__ void worker_waves_la(SM& sm, int wk, int lane, int nt
 #pragma unroll
   for (int s = 0; s < SLOTS; ++s)
     if (ti[s] == 0 && tj[s] == 0) publish_diag(s, 0);
+  if (kLateCov<T>) {
+    __syncthreads();  // Gb: stage free again
+    if (nt > 1) gen_column<T, NTHR - 64>(sm, stage, wtid, 1, 1, nt, nA, d, two_nu, sigma2, tau2);
+  }
   __syncthreads();  // P0
   for (int k = 0; k < nt; ++k) {
     refresh_slots<SLOTS>(ti, tj);
+    if (kLateCov<T>) add_staged(k + 1);  // staged during the previous step (or up front)
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
       if (tj[s] == k && ti[s] > k) {
@@ -500,6 +589,9 @@ __device__ __forceinline__ void worker_waves_la(SM& sm, int wk, int lane, int nt
         if (ti[s] == k + 1 && tj[s] == k + 1) publish_diag(s, k + 1);
       }
     }
+    // covariance column k+2 while the panel wave factors diagonal tile k+1
+    if (kLateCov<T> && k + 2 < nt)
+      gen_column<T, NTHR - 64>(sm, stage, wtid, k + 2, k + 2, nt, nA, d, two_nu, sigma2, tau2);
     __syncthreads();  // S4
   }
 }
@@ -574,8 +666,14 @@ __device__ __forceinline__ void worker_waves(SM& sm, int wk, int lane, int nt, i
     ti[s] = __builtin_amdgcn_readfirstlane(i);
     tj[s] = __builtin_amdgcn_readfirstlane(j);
   }
-  // covariance tiles, one tile column at a time: every thread of the
-  // workgroup builds entries into LDS (gen_column), owners copy theirs in.
+  // A slot holds G = sum_k L_ik L_jk^T - Sigma_ij.  In FP64 (kLateCov) the
+  // two parts are added in any order: slots start at zero and tile column j of
+  // Sigma is generated just before it is needed -- column 0 up front, column
+  // k+1 while the panel wave factors diagonal tile k (the workers would
+  // otherwise wait there).  In FP32 every column is generated first, so that
+  // the running sums shrink towards the Schur complement instead of growing
+  // towards Sigma (FP32 rounding of the updates stays relative to the smaller
+  // value).
   acc_t acc[SLOTS];
 #pragma unroll
   for (int s = 0; s < SLOTS; ++s) {
@@ -583,19 +681,22 @@ __device__ __forceinline__ void worker_waves(SM& sm, int wk, int lane, int nt, i
     for (int t = 0; t < 4; ++t) acc[s][t] = T(0);
   }
   SBV_PROF_DECL
-  for (int j = 0; j < nt; ++j) {
-    refresh_slots<SLOTS>(ti, tj);
-    gen_column<T, NTHR>(sm, 64 * (wk + 1) + lane, j, j, nt, nA, d, two_nu, sigma2, tau2);
-    __syncthreads();  // G1: column j staged
+  if (!kLateCov<T>) {
+    // every thread of the workgroup builds a column into LDS, owners copy theirs in
+    for (int j = 0; j < nt; ++j) {
+      refresh_slots<SLOTS>(ti, tj);
+      gen_column<T, NTHR>(sm, sm.panel, 64 * (wk + 1) + lane, j, j, nt, nA, d, two_nu, sigma2, tau2);
+      __syncthreads();  // G1: column j staged
 #pragma unroll
-    for (int s = 0; s < SLOTS; ++s) {
-      if (tj[s] == j) {
-        const T* src = sm.panel + 256 * ti[s];
+      for (int s = 0; s < SLOTS; ++s) {
+        if (tj[s] == j) {
+          const T* src = sm.panel + 256 * ti[s];
 #pragma unroll
-        for (int t = 0; t < 4; ++t) acc[s][t] = src[64 * t + lane];
+          for (int t = 0; t < 4; ++t) acc[s][t] = src[64 * t + lane];
+        }
       }
+      __syncthreads();  // G2: staging area free
     }
-    __syncthreads();  // G2: staging area free
   }
   if (PRE) {
     // large block: G += L_RP L_RP^T, one prefix column tile at a time
@@ -617,6 +718,23 @@ __device__ __forceinline__ void worker_waves(SM& sm, int wk, int lane, int nt, i
       __syncthreads();  // P2
     }
   }
+  // covariance column j is staged by the workers in the second half of the
+  // panel (`stage`) and added by the owners of its tiles
+  T* stage = sm.panel + Smem<T, NTM, GRAD>::kPanel;
+  const int wtid = 64 * wk + lane;
+  if (kLateCov<T>) {
+    gen_column<T, NTHR - 64>(sm, stage, wtid, 0, 0, nt, nA, d, two_nu, sigma2, tau2);
+    __syncthreads();  // G0: covariance column 0 staged
+    refresh_slots<SLOTS>(ti, tj);
+#pragma unroll
+    for (int s = 0; s < SLOTS; ++s) {
+      if (tj[s] == 0) {
+        const T* src = stage + 256 * ti[s];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) acc[s][t] += src[64 * t + lane];
+      }
+    }
+  }
   SBV_PROF(8, wk == 0);
   for (int k = 0; k < nt; ++k) {
     refresh_slots<SLOTS>(ti, tj);
@@ -629,8 +747,20 @@ __device__ __forceinline__ void worker_waves(SM& sm, int wk, int lane, int nt, i
     }
     __syncthreads();  // S1
     SBV_PROF(9, wk == 0);
+    // covariance column k+1 while the panel wave factors diagonal tile k
+    if (kLateCov<T> && k + 1 < nt)
+      gen_column<T, NTHR - 64>(sm, stage, wtid, k + 1, k + 1, nt, nA, d, two_nu, sigma2, tau2);
+    SBV_PROF(15, wk == 0);
     __syncthreads();  // S2
     SBV_PROF(10, wk == 0);
+#pragma unroll
+    for (int s = 0; s < SLOTS; ++s) {
+      if (kLateCov<T> && tj[s] == k + 1) {
+        const T* src = stage + 256 * ti[s];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) acc[s][t] += src[64 * t + lane];
+      }
+    }
     // column-k TRSM: L_ik = A_ik L_kk^{-T}, published in operand layout
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
@@ -900,7 +1030,7 @@ __device__ __forceinline__ void prefix_panel_wave(SM& sm, int lane, int p, int c
                            th);
     __syncthreads();  // C0: chunk coordinates staged
     for (int j = 0; j < p; ++j) {
-      gen_column<T, NTHR>(sm, lane, j, ch == 0 ? j : p, ntl, nAl, d, S.two_nu, sigma2, tau2);
+      gen_column<T, NTHR>(sm, sm.panel, lane, j, ch == 0 ? j : p, ntl, nAl, d, S.two_nu, sigma2, tau2);
       __syncthreads();  // G1
       __syncthreads();  // G2
     }
@@ -968,7 +1098,7 @@ __device__ __forceinline__ void prefix_worker_waves(SM& sm, int wk, int lane, in
     for (int j = 0; j < p; ++j) {
       refresh_slots<SLOTS>(ti, tj);
       const int i0 = ch == 0 ? j : p;
-      gen_column<T, NTHR>(sm, tid, j, i0, ntl, nAl, d, S.two_nu, sigma2, tau2);
+      gen_column<T, NTHR>(sm, sm.panel, tid, j, i0, ntl, nAl, d, S.two_nu, sigma2, tau2);
       __syncthreads();  // G1: column j staged
 #pragma unroll
       for (int s = 0; s < SLOTS; ++s) {

@@ -1,6 +1,8 @@
 """Larger measurements beyond the benchmark's default run.
 
+    python -m paper_2504_12004_amd.experiments c3 --out results/c3.json
     python -m paper_2504_12004_amd.experiments c4 --out results/c4.json
+    python -m paper_2504_12004_amd.experiments c5 --out results/c5.json
 
 c4: n = 5e6, d = 10, Matern-5/2, 250,000 k-means blocks of 5..60 points,
 m = 400 (joint sets up to 460, the large path).  Observations from the
@@ -119,16 +121,210 @@ def c4(out_path, reps=3, fits=True):
     log(f"wrote {out_path}")
 
 
+def _prior(g, d):
+    """Parameter prior of the warm-start study: beta_k ~ logU[0.05, 3],
+    sigma^2 ~ logU[0.5, 2], tau^2 ~ logU[1e-6, 1e-2], nu = 5/2."""
+    from paper_2504_12004_amd import synth
+    beta = synth.log_uniform(g, 0.05, 3.0, d)
+    return synth.theta_vector(beta, synth.log_uniform(g, 0.5, 2.0), synth.log_uniform(g, 1e-6, 1e-2))
+
+
+def c5(out_path, n_train=4096, n_val=512, n_app=2_000_000, epochs=200, nm_evals=500):
+    """Learned warm start.  Training: n_train datasets of n = 2e4 points in
+    [0,1]^10, theta from the prior, y from the conditional simulator (1000
+    k-means blocks, m_gen = 100); 64 summary features each; the 64-256-256-256-12
+    GELU network trained with Adam (lr 1e-3, batch 256) on all but n_val sets.
+    Application: a fresh dataset of n_app points (theta* from the prior, y from
+    the simulator on an independent structure with m_gen = 200); the network
+    predicts theta from its features; one evaluation structure (m = 400,
+    blocks of 5..60 points, built at the predicted ranges) is shared by every
+    fit: Nelder-Mead FP64 and FP32 and L-BFGS FP64 and FP32 from the cold start
+    (beta_k = 1, sigma^2 = var(y), tau^2 = 1e-3 var(y)), and L-BFGS FP32 from
+    the network's prediction; FP32 fits end with an FP64 polish and every
+    optimum is judged by one FP64 evaluation."""
+    import torch
+    torch.cuda.init()
+    from paper_2504_12004_amd import sbv, synth
+    d, nt_pts, two_nu = 10, 20000, 5
+    g = np.random.default_rng(5)
+    feats = np.empty((n_train, 4 + 5 * (d + 2)), np.float32)
+    targ = np.empty((n_train, d + 2), np.float32)
+    t0 = time.perf_counter()
+    for j in range(n_train):
+        X = g.random((nt_pts, d))
+        th = _prior(g, d)
+        xi = g.standard_normal(nt_pts)
+        Bg = sbv.sbv_build_blocks(X, None, np.exp(th[:d]), 1000, 100, method=sbv.SBV_KMEANS, lloyd_iters=1,
+                                  seed=1000003 + j)
+        y = sbv.sbv_sample(Bg, th, two_nu, xi)
+        Bg.free()
+        feats[j] = sbv.sbv_features(X, y, nt_pts, seed=j)
+        targ[j] = th
+        if (j + 1) % 256 == 0:
+            log(f"training sets: {j + 1}/{n_train} ({time.perf_counter() - t0:.0f} s)")
+    n_val = min(n_val, n_train // 8)
+    res = {"training_sets": n_train, "validation_sets": n_val, "data_seconds": time.perf_counter() - t0}
+    ntr = n_train - n_val
+    mlp = sbv.sbv_mlp_create(feats.shape[1], 256, 3, d + 2, seed=5)
+    t0 = time.perf_counter()
+    loss = sbv.sbv_mlp_train(mlp, feats[:ntr], targ[:ntr], epochs, batch=256, lr=1e-3, seed=5)
+    res["train_seconds"] = time.perf_counter() - t0
+    res["final_train_loss_standardised"] = loss
+    pred = sbv.sbv_mlp_predict(mlp, feats[ntr:])
+    rm = np.sqrt(np.mean((pred - targ[ntr:]) ** 2, axis=0))
+    rb = np.sqrt(np.mean((targ[:ntr].mean(axis=0) - targ[ntr:]) ** 2, axis=0))
+    res["val_rmse_log_theta"] = rm.tolist()
+    res["val_rmse_mean_predictor"] = rb.tolist()
+    log(f"network: train loss {loss:.4f}, validation RMSE (log theta) mean {rm.mean():.3f} "
+        f"vs mean predictor {rb.mean():.3f}")
+    sbv.sbv_mlp_save(mlp, out_path + ".mlp")
+
+    # application
+    ga = np.random.default_rng(6)
+    X = ga.random((n_app, d))
+    th_true = _prior(ga, d)
+    xi = ga.standard_normal(n_app)
+    K = n_app // 20
+    Bg = sbv.sbv_build_blocks(X, None, np.exp(th_true[:d]), K, 200, method=sbv.SBV_KMEANS, lloyd_iters=1,
+                              min_bs=5, max_bs=60, seed=7)
+    y = sbv.sbv_sample(Bg, th_true, two_nu, xi)
+    Bg.free()
+    f_app = sbv.sbv_features(X, y, nt_pts, seed=11)
+    th_warm = sbv.sbv_mlp_predict(mlp, f_app[None, :].astype(np.float32))[0].astype(np.float64)
+    mlp.free()
+    var_y = float(np.var(y))
+    th_cold = np.r_[np.zeros(d), np.log(var_y), np.log(1e-3 * var_y)]
+    res["application"] = {"n": n_app, "K": K, "m": 400, "theta_true": th_true.tolist(),
+                          "theta_warm": th_warm.tolist(), "theta_cold": th_cold.tolist(),
+                          "warm_abs_err": np.abs(th_warm - th_true).tolist(),
+                          "cold_abs_err": np.abs(th_cold - th_true).tolist()}
+    t0 = time.perf_counter()
+    B = sbv.sbv_build_blocks(X, y, np.exp(th_warm[:d]), K, 400, method=sbv.SBV_KMEANS, lloyd_iters=2, min_bs=5,
+                             max_bs=60, seed=8)
+    res["application"]["build_seconds"] = time.perf_counter() - t0
+    log(f"application structure: n = {n_app}, K = {B.K}, built in {res['application']['build_seconds']:.1f} s")
+    res["application"]["loglik_fp64_at_true"] = float(sbv.sbv_loglik(B, th_true, two_nu)[0])
+    ckpt = out_path + ".ckpt"
+    legs = [("nm_fp64_cold", sbv.SBV_NELDER_MEAD, sbv.SBV_FP64, False, th_cold, nm_evals),
+            ("nm_fp32_cold_polish64", sbv.SBV_NELDER_MEAD, sbv.SBV_FP32, True, th_cold, nm_evals),
+            ("lbfgs_fp64_cold", sbv.SBV_LBFGS, sbv.SBV_FP64, False, th_cold, 400),
+            ("lbfgs_fp32_cold_polish64", sbv.SBV_LBFGS, sbv.SBV_FP32, True, th_cold, 400),
+            ("lbfgs_fp32_warm_polish64", sbv.SBV_LBFGS, sbv.SBV_FP32, True, th_warm, 400)]
+    fits = {}
+    for name, opt, prec, polish, x0, me in legs:
+        if os.path.exists(ckpt):
+            os.remove(ckpt)
+        o = sbv.make_fit_opts(optimizer=opt, prec=prec, fp64_polish=polish, max_evals=me, ftol=1e-12,
+                              gtol=1e-6 * n_app, checkpoint_path=ckpt)
+        log(f"fit {name}")
+        th, l64, ne, sec, conv = sbv.sbv_fit(B, x0, two_nu, o)
+        fits[name] = {"seconds": sec, "evals": ne, "loglik_fp64": l64, "converged": conv, "theta": th.tolist()}
+        log(f"fit {name}: {sec:.1f} s, {ne} evals, l64 {l64:.6f}, converged {conv}")
+    if os.path.exists(ckpt):
+        os.remove(ckpt)
+    base = fits["nm_fp64_cold"]["loglik_fp64"]
+    for k in fits:
+        fits[k]["rel_gap_vs_nm_fp64"] = (fits[k]["loglik_fp64"] - base) / abs(base)
+        fits[k]["gap_nats_vs_nm_fp64"] = fits[k]["loglik_fp64"] - base
+    res["application"]["fits"] = fits
+    B.free()
+    with open(out_path, "w") as f:
+        json.dump(res, f, indent=1)
+    log(f"wrote {out_path}")
+
+
+def c3(out_path, reps=3):
+    """Batched evaluation of 64 datasets (n_j in 5e4..4e5, d_j in {5, 10, 20},
+    nu_j in {3/2, 5/2}, m_j in {100, 200, 400}, 20-point k-means blocks bounded
+    to 5..60; y from the simulator on an independent structure with m_gen = 60).
+    One evaluation of all 64 = one replay of the captured graph of the
+    combined plan (size buckets shared across datasets, autotuned), against
+    64 per-dataset evaluations queued one after the other on the same stream,
+    in FP32 (FP64 accumulation, FP64 fallback) and in FP64."""
+    import torch
+    torch.cuda.init()
+    from paper_2504_12004_amd import sbv, synth
+    recipes = synth.multi_datasets(64, 3)
+    hs, ths, tns = [], [], []
+    t0 = time.perf_counter()
+    for j, r in enumerate(recipes):
+        X, xi = synth.inputs_for(r)
+        th, d = r["theta"], r["d"]
+        beta = np.exp(th[:d])
+        Bg = sbv.sbv_build_blocks(X, None, beta, r["K"], 60, method=sbv.SBV_KMEANS, lloyd_iters=1,
+                                  min_bs=r["min_bs"], max_bs=r["max_bs"], seed=r["seed"] + 7919)
+        y = sbv.sbv_sample(Bg, th, r["two_nu"], xi)
+        Bg.free()
+        hs.append(sbv.sbv_build_blocks(X, y, beta, r["K"], r["m"], method=sbv.SBV_KMEANS, lloyd_iters=2,
+                                       min_bs=r["min_bs"], max_bs=r["max_bs"], seed=r["seed"]))
+        ths.append(th)
+        tns.append(r["two_nu"])
+        if (j + 1) % 8 == 0:
+            log(f"datasets built: {j + 1}/64 ({time.perf_counter() - t0:.0f} s)")
+    res = {"datasets": 64, "total_points": int(sum(r["n"] for r in recipes)),
+           "build_seconds": time.perf_counter() - t0}
+    flops, _ = sbv.sbv_plan_flops(hs, tns)
+    res["algorithmic_tflop_per_eval"] = float(np.sum(flops)) / 1e12
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    th_all = torch.tensor(np.concatenate(ths), dtype=torch.float64, device=dev)
+    offs = np.r_[0, np.cumsum([len(t) for t in ths])]
+    for name, prec in (("fp32", sbv.SBV_FP32), ("fp64", sbv.SBV_FP64)):
+        tiles = sbv.sbv_autotune(hs, ths, tns, prec, reps=2)
+        out_b = torch.empty(64, dtype=torch.float64, device=dev)
+        out_s = torch.empty(64, dtype=torch.float64, device=dev)
+        for _ in range(2):
+            sbv.sbv_eval_graph_dev(hs, th_all, tns, out_b, prec, stream=stream)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            sbv.sbv_eval_graph_dev(hs, th_all, tns, out_b, prec, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        t_b = e0.elapsed_time(e1) / reps
+
+        def seq():
+            for j in range(64):
+                sbv.sbv_loglik_dev(hs[j], th_all[offs[j]:offs[j + 1]], tns[j], out_s[j:j + 1], prec, stream)
+        seq()
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(reps):
+            seq()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        t_s = e0.elapsed_time(e1) / reps
+        ob, os_ = out_b.cpu().numpy(), out_s.cpu().numpy()
+        res[name] = {"batched_graph_ms": t_b, "sequential_ms": t_s, "speedup": t_s / t_b,
+                     "batched_algorithmic_tflops": float(np.sum(flops)) / (t_b * 1e-3) / 1e12,
+                     "max_rel_diff_batched_vs_sequential": float(np.max(np.abs(ob - os_) / np.abs(os_))),
+                     "autotuned_tiles": [int(t) for t in tiles]}
+        log(f"{name}: batched graph {t_b:.1f} ms, sequential {t_s:.1f} ms, "
+            f"{res[name]['batched_algorithmic_tflops']:.2f} TFLOP/s")
+    for b in hs:
+        b.free()
+    with open(out_path, "w") as f:
+        json.dump(res, f, indent=1)
+    log(f"wrote {out_path}")
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("what", choices=["c4"])
+    ap.add_argument("what", choices=["c3", "c4", "c5"])
     ap.add_argument("--out", required=True)
     ap.add_argument("--reps", type=int, default=3)
     ap.add_argument("--no-fits", action="store_true")
+    ap.add_argument("--train-sets", type=int, default=4096)
+    ap.add_argument("--app-n", type=int, default=2_000_000)
     a = ap.parse_args()
     os.makedirs(os.path.dirname(os.path.abspath(a.out)), exist_ok=True)
     if a.what == "c4":
         c4(a.out, a.reps, not a.no_fits)
+    elif a.what == "c3":
+        c3(a.out, a.reps)
+    elif a.what == "c5":
+        c5(a.out, n_train=a.train_sets, n_app=a.app_n)
 
 
 if __name__ == "__main__":
