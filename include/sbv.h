@@ -155,7 +155,8 @@ typedef struct {
   int32_t optimizer;          /* SBV_NELDER_MEAD (values only) or SBV_LBFGS (values + gradients)   */
   int32_t prec;               /* SBV_FP64 or SBV_FP32 evaluations                                  */
   int32_t fp64_polish;        /* with SBV_FP32: continue in FP64 from the FP32 optimum; the FP32    */
-                              /* phase then stops at a relative change of max(ftol, 1e-7)          */
+                              /* phase then stops at a relative change of max(ftol, 1e-7), and for */
+                              /* L-BFGS at its first failed line search (8 trials each)            */
   int32_t max_evals;          /* objective evaluations allowed (-> SBV_E_NOCONV when reached)       */
   double ftol;                /* Nelder-Mead: stop when the simplex spread of -l is <= ftol |l|;   */
                               /* L-BFGS: stop when one iteration changes -l by <= ftol |l|         */

@@ -258,7 +258,7 @@ double cubic_min(double a, double fa, double ga, double b, double fb, double gb)
 
 // Returns the accepted step (0 if none) and leaves x, f, g at the new point.
 double wolfe_search(Objective& obj, std::vector<double>& x, double& f, std::vector<double>& g,
-                    const std::vector<double>& p, double a1, int64_t max_evals) {
+                    const std::vector<double>& p, double a1, int64_t max_evals, int max_trials = 30) {
   const double c1 = 1e-4, c2 = 0.9;
   const double f0 = f, g0 = dot(g, p);
   if (!(g0 < 0.0)) return 0.0;
@@ -276,7 +276,7 @@ double wolfe_search(Objective& obj, std::vector<double>& x, double& f, std::vect
     (void)aa;
   };
   auto zoom = [&](double lo, double flo, double glo, double hi, double fhi, double ghi) -> double {
-    for (int it = 0; it < 30 && obj.evals < max_evals; ++it) {
+    for (int it = 0; it < max_trials && obj.evals < max_evals; ++it) {
       double aj = std::isfinite(fhi) && std::isfinite(ghi) ? cubic_min(lo, flo, glo, hi, fhi, ghi) : 0.5 * (lo + hi);
       double fj, gj;
       phi(aj, fj, gj);
@@ -312,7 +312,7 @@ double wolfe_search(Objective& obj, std::vector<double>& x, double& f, std::vect
     }
     return 0.0;
   };
-  for (int it = 0; it < 30 && obj.evals < max_evals; ++it) {
+  for (int it = 0; it < max_trials && obj.evals < max_evals; ++it) {
     double fa, ga;
     phi(a, fa, ga);
     if (!std::isfinite(fa)) {  // outside the domain (e.g. not positive definite): back off
@@ -334,7 +334,11 @@ double wolfe_search(Objective& obj, std::vector<double>& x, double& f, std::vect
   return 0.0;
 }
 
-sbv_status lbfgs(Objective& obj, std::vector<double>& x, const sbv_fit_opts& o, double& fbest, bool& converged) {
+// coarse: a phase that a finer one will finish (FP32 before an FP64 polish):
+// line searches get a few trials and a failed one ends the phase instead of
+// restarting along steepest descent.
+sbv_status lbfgs(Objective& obj, std::vector<double>& x, const sbv_fit_opts& o, double& fbest, bool& converged,
+                 bool coarse = false) {
   const int n = (int)x.size();
   const int M = o.lbfgs_m > 0 ? o.lbfgs_m : 10;
   std::vector<double> g(n);
@@ -399,9 +403,9 @@ sbv_status lbfgs(Objective& obj, std::vector<double>& x, const sbv_fit_opts& o, 
     }
     const std::vector<double> xold = x, gold = g;
     const double fold = f;
-    double a = wolfe_search(obj, x, f, g, p, 1.0, o.max_evals);
+    double a = wolfe_search(obj, x, f, g, p, 1.0, o.max_evals, coarse ? 8 : 30);
     if (a == 0.0) {
-      if (!S.empty()) {  // retry once along steepest descent
+      if (!S.empty() && !coarse) {  // retry once along steepest descent
         S.clear();
         Y.clear();
         continue;
@@ -431,9 +435,9 @@ sbv_status lbfgs(Objective& obj, std::vector<double>& x, const sbv_fit_opts& o, 
 }
 
 sbv_status run_minimize(int32_t method, std::vector<double>& x, Objective& obj, const sbv_fit_opts& o,
-                        double& fbest, bool& converged) {
+                        double& fbest, bool& converged, bool coarse = false) {
   if (method == SBV_NELDER_MEAD) return nelder_mead(obj, x, o, fbest, converged);
-  if (method == SBV_LBFGS) return lbfgs(obj, x, o, fbest, converged);
+  if (method == SBV_LBFGS) return lbfgs(obj, x, o, fbest, converged, coarse);
   return sbv_internal_fail(SBV_E_INVAL, "unknown optimizer");
 }
 
@@ -502,8 +506,9 @@ sbv_status sbv_fit(sbv_blocks set, const double* theta0, int32_t two_nu, const s
   // the block terms hides real progress and line searches only fail.
   constexpr double kFp32Ftol = 1e-7;
   sbv_fit_opts first = *o;
-  if (o->fp64_polish && o->prec == SBV_FP32) first.ftol = std::max(o->ftol, kFp32Ftol);
-  sbv_status st = run_minimize(o->optimizer, x, obj, first, fb, conv);
+  const bool coarse = o->fp64_polish && o->prec == SBV_FP32;
+  if (coarse) first.ftol = std::max(o->ftol, kFp32Ftol);
+  sbv_status st = run_minimize(o->optimizer, x, obj, first, fb, conv, coarse);
   if (st) return st;
   if (c.last != SBV_OK) return c.last;
   int64_t evals = obj.evals;

@@ -167,15 +167,24 @@ def c5(out_path, n_train=4096, n_val=512, n_app=2_000_000, epochs=200, nm_evals=
     ntr = n_train - n_val
     mlp = sbv.sbv_mlp_create(feats.shape[1], 256, 3, d + 2, seed=5)
     t0 = time.perf_counter()
-    loss = sbv.sbv_mlp_train(mlp, feats[:ntr], targ[:ntr], epochs, batch=256, lr=1e-3, seed=5)
+    # rounds of 10 epochs (Adam's state carries over); keep the parameters with
+    # the lowest validation error (early stopping)
+    best, best_p, best_ep, loss = np.inf, None, 0, None
+    for ep in range(10, epochs + 1, 10):
+        loss = sbv.sbv_mlp_train(mlp, feats[:ntr], targ[:ntr], 10, batch=256, lr=1e-3, seed=5 + ep)
+        err = float(np.mean((sbv.sbv_mlp_predict(mlp, feats[ntr:]) - targ[ntr:]) ** 2))
+        if err < best:
+            best, best_p, best_ep = err, sbv.sbv_mlp_get_params(mlp), ep
+    sbv.sbv_mlp_set_params(mlp, best_p)
     res["train_seconds"] = time.perf_counter() - t0
     res["final_train_loss_standardised"] = loss
+    res["epochs_kept"] = best_ep
     pred = sbv.sbv_mlp_predict(mlp, feats[ntr:])
     rm = np.sqrt(np.mean((pred - targ[ntr:]) ** 2, axis=0))
     rb = np.sqrt(np.mean((targ[:ntr].mean(axis=0) - targ[ntr:]) ** 2, axis=0))
     res["val_rmse_log_theta"] = rm.tolist()
     res["val_rmse_mean_predictor"] = rb.tolist()
-    log(f"network: train loss {loss:.4f}, validation RMSE (log theta) mean {rm.mean():.3f} "
+    log(f"network: kept epoch {best_ep}, validation RMSE (log theta) mean {rm.mean():.3f} "
         f"vs mean predictor {rb.mean():.3f}")
     sbv.sbv_mlp_save(mlp, out_path + ".mlp")
 
