@@ -205,6 +205,30 @@ __device__ __forceinline__ double row_all(double v, int gj) {
 }
 __device__ __forceinline__ float row_all(float v, int gj) { return __uint_as_float(row_all_u(__float_as_uint(v), gj)); }
 
+// Sum of the four rows' values at the same position within the row, left in
+// every row: rows (0 1 2 3) -> permlane16_swap pairs (0,1) and (2,3), then
+// permlane32_swap pairs the two halves.
+__device__ __forceinline__ double rows_sum(double v) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+  const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)u, (unsigned)u, false, false);
+  const auto hi = __builtin_amdgcn_permlane16_swap((unsigned)(u >> 32), (unsigned)(u >> 32), false, false);
+  const double s1 = __longlong_as_double((long long)(((unsigned long long)hi[0] << 32) | lo[0])) +
+                    __longlong_as_double((long long)(((unsigned long long)hi[1] << 32) | lo[1]));
+  const unsigned long long w = (unsigned long long)__double_as_longlong(s1);
+  const auto lo2 = __builtin_amdgcn_permlane32_swap((unsigned)w, (unsigned)w, false, false);
+  const auto hi2 = __builtin_amdgcn_permlane32_swap((unsigned)(w >> 32), (unsigned)(w >> 32), false, false);
+  return __longlong_as_double((long long)(((unsigned long long)hi2[0] << 32) | lo2[0])) +
+         __longlong_as_double((long long)(((unsigned long long)hi2[1] << 32) | lo2[1]));
+}
+__device__ __forceinline__ float rows_sum(float v) {
+  const unsigned u = __float_as_uint(v);
+  const auto a = __builtin_amdgcn_permlane16_swap(u, u, false, false);
+  const float s1 = __uint_as_float(a[0]) + __uint_as_float(a[1]);
+  const unsigned w = __float_as_uint(s1);
+  const auto b = __builtin_amdgcn_permlane32_swap(w, w, false, false);
+  return __uint_as_float(b[0]) + __uint_as_float(b[1]);
+}
+
 // Factor the 16x16 SPD tile in sm.diag on one wave with all 64 lanes: lane
 // (r, g) = (l % 16, l / 16) holds columns c = g + 4q (q = 0..3) of row r.
 // Right-looking pivots; by symmetry of the trailing matrix the column-j
@@ -236,30 +260,43 @@ __device__ __forceinline__ void factor_diag(SM& sm, T* negM_out, int lane, int k
     if (piv <= tau * (j < nreal ? diag0 : T(1))) low = 1;
     const T rs = rsqrt_nr(piv);
     const T sq = piv * rs;
-    // A[r][j] of my row and row j of my columns, before this step's update
+    // A[r][j] of my row and row j of my columns, before this step's update.
+    // Register q holds columns 4q..4q+3 (q and j are constants after
+    // unrolling): it is final once 4q + 3 < j, lies wholly right of the pivot
+    // once 4q > j, and holds column j for q = qj.
     const T arj = row_all(a[qj], gj);
     T ajc[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) ajc[q] = row_lane(a[q], j);
+    for (int q = 0; q < 4; ++q)
+      if (4 * q + 3 > j) ajc[q] = row_lane(a[q], j);
     const T lrj = (r == j) ? sq : arj * rs;  // L[r][j] (r >= j)
+    const T lrm = (r > j) ? lrj : T(0);      // the same below the pivot, 0 elsewhere
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const int c = g + 4 * q;
-      if (c > j) a[q] = (r > j) ? a[q] - lrj * (ajc[q] * rs) : a[q];
-      if (c == j) a[q] = (r >= j) ? lrj : a[q];
+      if (4 * q + 3 < j) continue;
+      if (4 * q > j) {
+        a[q] -= lrm * (ajc[q] * rs);
+      } else {
+        const int c = g + 4 * q;
+        if (c > j) a[q] = (r > j) ? a[q] - lrj * (ajc[q] * rs) : a[q];
+        if (c == j) a[q] = (r >= j) ? lrj : a[q];
+      }
     }
-    // row j of X is final after scaling, then eliminated from the rows below
+    // row j of X is final after scaling, then eliminated from the rows below;
+    // X[j][c] = 0 for c > j, so registers with 4q > j take no part
+    const T srow = (r == j) ? rs : T(1);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) x[q] = (r == j) ? x[q] * rs : x[q];
+    for (int q = 0; q < 4; ++q)
+      if (4 * q <= j) x[q] *= srow;
     T xjc[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) xjc[q] = row_lane(x[q], j);
+    for (int q = 0; q < 4; ++q)
+      if (4 * q <= j) xjc[q] = row_lane(x[q], j);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) x[q] = (r > j) ? x[q] - lrj * xjc[q] : x[q];
-    T zj;
-    if (!SAMPLE) {
-      zj = rlane(yr, j) * rs;
-    } else {
+    for (int q = 0; q < 4; ++q)
+      if (4 * q <= j) x[q] -= lrm * xjc[q];
+    if (SAMPLE) {
+      T zj;
       // conditional simulation: rows of J are solved (w = z), rows of B take
       // w = xi and emit y = L_jj xi - v, v being the eliminated part so far
       const int R = kTile * k + j;
@@ -271,8 +308,16 @@ __device__ __forceinline__ void factor_diag(SM& sm, T* negM_out, int lane, int k
         zj = xj;
         if (r == j) *ysim = sq * xj - vj;
       }
+      yr = (r == j) ? zj : (r > j ? yr - lrj * zj : yr);
     }
-    yr = (r == j) ? zj : (r > j ? yr - lrj * zj : yr);
+  }
+  if (!SAMPLE) {
+    // z_k = L_kk^{-1} y_k = X y_k: lane (r, g) sums X[r][c] y[c] over its
+    // columns c = g + 4q, then the four row groups are added
+    T part = T(0);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) part += x[q] * sm.yv[kTile * k + g + 4 * q];
+    yr = rows_sum(part);
   }
   // pivot L_rr lives in lane (r, r % 4), register r / 4
   T mine = a[0];
