@@ -114,6 +114,10 @@ __device__ unsigned long long g_phase[16];
   } while (0)
 #endif
 
+// Row stride of the diagonal tile in LDS: 17 elements, so that the 16 rows
+// (or columns) one instruction touches fall on different banks.
+constexpr int kDiagLd = 17;
+
 // Row stride of the right-hand-side chunk used by the adjoint solves (32
 // columns plus one of padding so that rows fall on different LDS banks).
 constexpr int kRS = 33;
@@ -134,7 +138,7 @@ struct Smem {
   // the next covariance column; right-hand-side chunk of the adjoint solves
   // (GRAD only)
   T panel[(GRAD && kRhs > 2 * kPanel) ? kRhs : 2 * kPanel];
-  T diag[256];                 // diagonal tile to factor (row-major)
+  T diag[16 * kDiagLd];        // diagonal tile to factor (row-major, padded rows)
   T negM[256];                 // -(L_kk^{-T}) in B-operand layout
   T zk[kTile];                 // solved z of the current tile row
   T zfull[GRAD ? NTM * kTile : 1];  // all of z = L^{-1} y (GRAD only)
@@ -248,7 +252,7 @@ __device__ __forceinline__ void factor_diag(SM& sm, T* negM_out, int lane, int k
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int c = g + 4 * q;
-    a[q] = sm.diag[r * 16 + c];
+    a[q] = sm.diag[r * kDiagLd + c];
     x[q] = (c == r) ? T(1) : T(0);
   }
   T yr = sm.yv[kTile * k + r];
@@ -374,15 +378,11 @@ __device__ __forceinline__ void gen_column(SM& sm, T* dst, int tid, int j, int i
   }
 }
 
-// Forward-solve update of the observations in rows r0..16nt-1 with the column
+// Forward-solve update of the observations in rows r0..r1-1 with the column
 // tile of L staged in the panel: y_rho -= L[rho][16k..16k+15] z_k, four rows
-// per lane as independent chains.
+// per lane as independent chains (y_update: rows r0..16nt-1 with z_k from LDS).
 template <typename T, class SM>
-__device__ __forceinline__ void y_update(SM& sm, int lane, int r0, int nt) {
-  T zk[16];
-#pragma unroll
-  for (int c = 0; c < 16; ++c) zk[c] = sm.zk[c];
-  const int r1 = kTile * nt;
+__device__ __forceinline__ void y_update_rows(SM& sm, int lane, int r0, int r1, const T (&zk)[16]) {
   for (int base = r0; base < r1; base += 256) {
     T v[4];
     int rho[4];
@@ -403,6 +403,13 @@ __device__ __forceinline__ void y_update(SM& sm, int lane, int r0, int nt) {
     for (int it = 0; it < 4; ++it)
       if (rho[it] < r1) sm.yv[rho[it]] = v[it];
   }
+}
+template <typename T, class SM>
+__device__ __forceinline__ void y_update(SM& sm, int lane, int r0, int nt) {
+  T zk[16];
+#pragma unroll
+  for (int c = 0; c < 16; ++c) zk[c] = sm.zk[c];
+  y_update_rows<T>(sm, lane, r0, kTile * nt, zk);
 }
 
 // Stage column tile k of a large block's prefix panel (nt tiles of L below
@@ -517,6 +524,7 @@ __device__ __forceinline__ void panel_wave_la(SM& sm, int lane, int nt, int mi, 
   __syncthreads();  // P0: step 0 factored
   for (int k = 0; k < nt; ++k) {
     __syncthreads();  // S3: column k of L published
+    // (the y update overlaps the wait for diagonal tile k+1)
     y_update<T>(sm, lane, kTile * (k + 1), nt);
     if (k + 1 < nt) factor_step(k + 1);
     __syncthreads();  // S4: trailing update and next diagonal done
@@ -593,7 +601,7 @@ __device__ __forceinline__ void worker_waves_la(SM& sm, int wk, int lane, int nt
   }
   auto publish_diag = [&](int s, int k) {
 #pragma unroll
-    for (int t = 0; t < 4; ++t) sm.diag[cl * 16 + MF<T>::row(g, t)] = -acc[s][t];
+    for (int t = 0; t < 4; ++t) sm.diag[cl * kDiagLd + MF<T>::row(g, t)] = -acc[s][t];
     __builtin_amdgcn_s_waitcnt(0);
     __builtin_amdgcn_wave_barrier();
     if (lane == 0) __atomic_store_n(&sm.la_flag, k, __ATOMIC_RELEASE);
@@ -787,7 +795,7 @@ __device__ __forceinline__ void worker_waves(SM& sm, int wk, int lane, int nt, i
     for (int s = 0; s < SLOTS; ++s) {
       if (ti[s] == k && tj[s] == k) {
 #pragma unroll
-        for (int t = 0; t < 4; ++t) sm.diag[cl * 16 + MF<T>::row(g, t)] = -acc[s][t];
+        for (int t = 0; t < 4; ++t) sm.diag[cl * kDiagLd + MF<T>::row(g, t)] = -acc[s][t];
       }
     }
     __syncthreads();  // S1
@@ -1032,7 +1040,7 @@ struct SmemP {
   T z[kLargeNTM * kTile * kMaxDim];  // scaled coordinates: P, then the current chunk of R
   T yv[kLargeNTM * kTile];           // observations of P, overwritten by the forward solve
   T panel[kLargeNTM * 256];          // generation staging / column k of L (operand layout)
-  T diag[256];                       // diagonal tile to factor (row-major)
+  T diag[16 * kDiagLd];              // diagonal tile to factor (row-major, padded rows)
   T negMs[kMaxPrefix * 256];         // -(L_kk^{-T}) of every diagonal tile of P
   T zk[kTile];
   T xi[1];  // unused: factor_diag's simulation branch is not instantiated here
@@ -1163,7 +1171,7 @@ __device__ __forceinline__ void prefix_worker_waves(SM& sm, int wk, int lane, in
         for (int s = 0; s < SLOTS; ++s) {
           if (ti[s] == k && tj[s] == k) {
 #pragma unroll
-            for (int t = 0; t < 4; ++t) sm.diag[cl * 16 + MF<T>::row(g, t)] = -acc[s][t];
+            for (int t = 0; t < 4; ++t) sm.diag[cl * kDiagLd + MF<T>::row(g, t)] = -acc[s][t];
           }
         }
         __syncthreads();  // S1

@@ -25,6 +25,13 @@ KERNEL_SOURCES = ("paper_2504_12004_amd/csrc/loglik_kernels.hip", "paper_2504_12
                   "paper_2504_12004_amd/build.py")
 BENCH_ARGS = ["--steps", "10", "--warmup", "2", "--no-cpu-baseline", "--fit-evals", "0", "--large-steps", "0"]
 COUNTER_BENCH_ARGS = ["--steps", "3", "--warmup", "1", "--no-cpu-baseline", "--fit-evals", "0", "--large-steps", "0"]
+# shader-sequencer counters, at most 8 per pass
+SQ_PASSES = {
+    "sq_a": ["SQ_INSTS_VALU", "SQ_INSTS_MFMA", "SQ_INSTS_LDS", "SQ_INSTS_SALU", "SQ_ACTIVE_INST_VALU",
+             "SQ_VALU_MFMA_BUSY_CYCLES", "SQ_BUSY_CU_CYCLES", "SQ_WAVE_CYCLES"],
+    "sq_b": ["SQ_WAIT_INST_ANY", "SQ_WAIT_ANY", "SQ_WAIT_INST_LDS", "SQ_LDS_BANK_CONFLICT", "SQ_ACTIVE_INST_LDS",
+             "SQ_INSTS_VALU_MFMA_MOPS_F64", "SQ_CYCLES", "SQ_WAVES"],
+}
 
 
 def kernel_source_hash():
@@ -49,7 +56,8 @@ def passes(out):
                              py, bench, "--copy-calibration"]),
         ("copy_write", 200, ["rocprofv3", "--pmc", "WRITE_SIZE", "-d", f"{out}/copy_write", "-o", "copy", "--",
                              py, bench, "--copy-calibration"]),
-    ]
+    ] + [(name, 400, ["rocprofv3", "--pmc"] + ctrs + ["-d", f"{out}/{name}", "-o", "bench", "--", py, bench]
+          + COUNTER_BENCH_ARGS) for name, ctrs in SQ_PASSES.items()]
 
 
 def run(out):
@@ -154,7 +162,7 @@ def summarize(out, write_dir):
     L = []
     L.append("# k_block_loglik on uneven_1m (n = 1e6, d = 10, K = 49981, m = 200, FP64)\n")
     L.append("Made by `python -m paper_2504_12004_amd.profiling run` then `... summarize`, which ran:\n")
-    for k in ("trace", "fetch", "write", "copy_fetch", "copy_write"):
+    for k in ("trace", "fetch", "write", "copy_fetch", "copy_write") + tuple(SQ_PASSES):
         if k in cmds:
             L.append(f"- {k}: `{cmds[k].replace(ROOT + '/', '').replace(sys.executable, 'python')}`")
     L.append("")
@@ -188,6 +196,28 @@ def summarize(out, write_dir):
         L.append(f"- HBM traffic per launch: {traffic / 1e9:.3f} GB; at the trace's average duration that is "
                  f"{traffic / (avg_ms * 1e-3) / 1e9:.0f} GB/s of the 8000 GB/s peak")
     L.append(f"- kernel source hash: `{res['kernel_source_hash']}`")
+    sq = {}
+    for name, ctrs in SQ_PASSES.items():
+        if not os.path.isdir(f"{out}/{name}"):
+            continue
+        con = _db(f"{out}/{name}")
+        for c in ctrs:
+            v = _counter(con, c).get(dom, [])
+            if v:
+                sq[c] = sum(v) / len(v)
+    if sq:
+        L.append("")
+        L.append("## Shader-sequencer counters of the dominant launch group (per launch)\n")
+        L.append("| counter | value |")
+        L.append("|---|---|")
+        for c, v in sq.items():
+            L.append(f"| {c} | {v:.4g} |")
+        if "SQ_VALU_MFMA_BUSY_CYCLES" in sq and "SQ_BUSY_CU_CYCLES" in sq and sq["SQ_BUSY_CU_CYCLES"] > 0:
+            L.append(f"\nSQ_VALU_MFMA_BUSY_CYCLES / SQ_BUSY_CU_CYCLES = "
+                     f"{sq['SQ_VALU_MFMA_BUSY_CYCLES'] / sq['SQ_BUSY_CU_CYCLES']:.3f}")
+        res["sq"] = sq
+        with open(os.path.join(write_dir, "k_block_loglik_uneven_1m_traffic.json"), "w") as f:
+            json.dump(res, f, indent=1)
     with open(os.path.join(write_dir, "k_block_loglik_uneven_1m.md"), "w") as f:
         f.write("\n".join(L) + "\n")
     print("\n".join(L))
