@@ -100,12 +100,14 @@ constexpr double kLog2Pi = 1.83787706640934548356065947281123527;
 // phase, summed over blocks.
 #ifdef SBV_PHASE_PROFILE
 __device__ unsigned long long g_phase[16];
+// per-workgroup accumulation in LDS (one writer per slot), flushed once per
+// workgroup: keeps the counters' own cost out of the phases they time
 #define SBV_PROF_DECL long long prof_t = clock64();
-#define SBV_PROF(slot, cond)                                                        \
-  do {                                                                              \
-    long long now_ = clock64();                                                     \
-    if ((cond) && (threadIdx.x & 63) == 0) atomicAdd(&g_phase[slot], (unsigned long long)(now_ - prof_t)); \
-    prof_t = now_;                                                                  \
+#define SBV_PROF(slot, cond)                                        \
+  do {                                                              \
+    long long now_ = clock64();                                     \
+    if ((cond) && (threadIdx.x & 63) == 0) sm.prof[slot] += (unsigned long long)(now_ - prof_t); \
+    prof_t = now_;                                                  \
   } while (0)
 #else
 #define SBV_PROF_DECL
@@ -144,6 +146,9 @@ struct Smem {
   T zfull[GRAD ? NTM * kTile : 1];  // all of z = L^{-1} y (GRAD only)
   T xi[NTM * kTile];                // innovations of the conditional simulator
   int la_flag;                      // lookahead: last diagonal step published
+#ifdef SBV_PHASE_PROFILE
+  unsigned long long prof[16];
+#endif
   T gv[GRAD ? NTM * kTile : 1];     // g = Q z_B accumulated over chunks (GRAD only)
 };
 
@@ -334,47 +339,68 @@ __device__ __forceinline__ void factor_diag(SM& sm, T* negM_out, int lane, int k
   for (int q = 0; q < 4; ++q) negM_out[opoff<T>(r, g + 4 * q)] = -x[q];
 }
 
+// N work items of gen_column computed together (independent chains for the
+// exp/sqrt latency): item e = (tile i0 + e/64, lane e%64), 4 entries each.
+template <typename T, int N, class SM>
+__device__ __forceinline__ void gen_items(SM& sm, T* dst, const int (&e)[N], int j, int i0, int nA, int d,
+                                          int two_nu, T sigma2, T tau2) {
+  int i[N], l[N], pb[N], pbc[N], pa[N][4], pac[N][4];
+  T r2[N][4];
+#pragma unroll
+  for (int n = 0; n < N; ++n) {
+    i[n] = i0 + (e[n] >> 6);
+    l[n] = e[n] & 63;
+    pb[n] = kTile * i[n] + (l[n] & 15);
+    pbc[n] = pb[n] < nA ? pb[n] : 0;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      pa[n][t] = kTile * j + MF<T>::row(l[n] >> 4, t);
+      pac[n][t] = pa[n][t] < nA ? pa[n][t] : 0;
+      r2[n][t] = T(0);
+    }
+  }
+  for (int k = 0; k < d; ++k) {
+#pragma unroll
+    for (int n = 0; n < N; ++n) {
+      const T zbk = sm.z[pbc[n] * d + k];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const T df = sm.z[pac[n][t] * d + k] - zbk;
+        r2[n][t] += df * df;
+      }
+    }
+  }
+#pragma unroll
+  for (int n = 0; n < N; ++n)
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      T v;
+      if (pa[n][t] >= nA || pb[n] >= nA) {
+        v = (pa[n][t] == pb[n]) ? T(-1) : T(0);
+      } else {
+        v = -(sigma2 * matern<T>(t_sqrt(r2[n][t]), two_nu));
+        if (pa[n][t] == pb[n]) v -= tau2;
+      }
+      dst[256 * i[n] + 64 * t + l[n]] = v;
+    }
+}
+
 template <typename T, int NTHR, class SM>
 __device__ __forceinline__ void gen_column(SM& sm, T* dst, int tid, int j, int i0, int nt, int nA, int d,
                                            int two_nu, T sigma2, T tau2) {
   // tiles (i, j) for i = i0..nt-1.  One work item = (tile i, lane l): the 4
   // entries of accumulator registers t = 0..3, which share the point
-  // 16i + l%16 (read once) and differ in the point 16j + row(l/16, t)
+  // 16i + l%16 (read once) and differ in the point 16j + row(l/16, t); a
+  // thread takes its items two at a time
   const int total = (nt - i0) * 64;
-  for (int e = tid; e < total; e += NTHR) {
-    const int i = i0 + (e >> 6);
-    const int l = e & 63;
-    const int pb = kTile * i + (l & 15);
-    const int pbc = pb < nA ? pb : 0;
-    T r2[4];
-    int pa[4];
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      pa[t] = kTile * j + MF<T>::row(l >> 4, t);
-      r2[t] = T(0);
-    }
-    int pac[4];
-#pragma unroll
-    for (int t = 0; t < 4; ++t) pac[t] = pa[t] < nA ? pa[t] : 0;
-    for (int k = 0; k < d; ++k) {
-      const T zbk = sm.z[pbc * d + k];
-#pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const T df = sm.z[pac[t] * d + k] - zbk;
-        r2[t] += df * df;
-      }
-    }
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      T v;
-      if (pa[t] >= nA || pb >= nA) {
-        v = (pa[t] == pb) ? T(-1) : T(0);
-      } else {
-        v = -(sigma2 * matern<T>(t_sqrt(r2[t]), two_nu));
-        if (pa[t] == pb) v -= tau2;
-      }
-      dst[256 * i + 64 * t + l] = v;
-    }
+  int e = tid;
+  for (; e + NTHR < total; e += 2 * NTHR) {
+    const int ee[2] = {e, e + NTHR};
+    gen_items<T, 2>(sm, dst, ee, j, i0, nA, d, two_nu, sigma2, tau2);
+  }
+  if (e < total) {
+    const int ee[1] = {e};
+    gen_items<T, 1>(sm, dst, ee, j, i0, nA, d, two_nu, sigma2, tau2);
   }
 }
 
@@ -937,6 +963,10 @@ __global__ __launch_bounds__(NW * 64) void k_block_loglik(const SetDesc* __restr
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int total = PRE ? min(max(*count - L.off, 0), L.nb) : *count;
   const WorkItem* itm = PRE ? items + L.off : items;
+#ifdef SBV_PHASE_PROFILE
+  if (tid < 16) sm.prof[tid] = 0ull;
+  __syncthreads();
+#endif
 
   for (int it = blockIdx.x; it < total; it += gridDim.x) {
     const WorkItem w = itm[it];
@@ -984,7 +1014,7 @@ __global__ __launch_bounds__(NW * 64) void k_block_loglik(const SetDesc* __restr
     if (tid == 0) sm.la_flag = -1;
     __syncthreads();
 #ifdef SBV_PHASE_PROFILE
-    if (tid == 0) atomicAdd(&g_phase[14], 1ull);  // blocks processed
+    if (tid == 0) sm.prof[14] += 1ull;  // blocks processed
 #endif
 
     if (wave == 0) {
@@ -1019,6 +1049,10 @@ __global__ __launch_bounds__(NW * 64) void k_block_loglik(const SetDesc* __restr
     }
     __syncthreads();
   }
+#ifdef SBV_PHASE_PROFILE
+  __syncthreads();
+  if (tid < 16) atomicAdd(&g_phase[tid], sm.prof[tid]);
+#endif
 }
 
 // ---- large blocks: elimination of the prefix --------------------------------
