@@ -65,8 +65,10 @@ struct MF<float> {
 // Offset inside a 256-entry operand tile of element (r, c), c being the K index.
 template <typename T>
 __device__ __forceinline__ int opoff(int r, int c) {
-  return 64 * MF<T>::qof(c) + 16 * MF<T>::gof(c) + r;
+  return 68 * MF<T>::qof(c) + 17 * MF<T>::gof(c) + r;
 }
+// Offset of lane l's operand in chunk q of a tile: 68 q + oplane(l).
+__device__ __forceinline__ int oplane(int lane) { return 17 * (lane >> 4) + (lane & 15); }
 
 __device__ __forceinline__ double rlane(double v, int l) {
   unsigned long long u = (unsigned long long)__double_as_longlong(v);
@@ -132,7 +134,7 @@ constexpr bool kLateCov = sizeof(T) == 8;
 
 template <typename T, int NTM, bool GRAD = false>
 struct Smem {
-  static constexpr int kPanel = NTM * 256;
+  static constexpr int kPanel = NTM * kOpT;
   static constexpr int kRhs = NTM * kTile * kRS;
   T z[NTM * kTile * kMaxDim];  // scaled coordinates of A (padded rows unused)
   T yv[NTM * kTile];           // observations, overwritten by the forward solve
@@ -141,7 +143,7 @@ struct Smem {
   // (GRAD only)
   T panel[(GRAD && kRhs > 2 * kPanel) ? kRhs : 2 * kPanel];
   T diag[16 * kDiagLd];        // diagonal tile to factor (row-major, padded rows)
-  T negM[256];                 // -(L_kk^{-T}) in B-operand layout
+  T negM[kOpT];                // -(L_kk^{-T}) in B-operand layout
   T zk[kTile];                 // solved z of the current tile row
   T zfull[GRAD ? NTM * kTile : 1];  // all of z = L^{-1} y (GRAD only)
   T xi[NTM * kTile];                // innovations of the conditional simulator
@@ -422,7 +424,7 @@ __device__ __forceinline__ void y_update_rows(SM& sm, int lane, int r0, int r1, 
 #pragma unroll
       for (int it = 0; it < 4; ++it) {
         const int rr = rho[it] < r1 ? rho[it] : r0;
-        v[it] -= sm.panel[256 * (rr >> 4) + opoff<T>(rr & 15, c)] * zk[c];
+        v[it] -= sm.panel[kOpT * (rr >> 4) + opoff<T>(rr & 15, c)] * zk[c];
       }
     }
 #pragma unroll
@@ -442,8 +444,8 @@ __device__ __forceinline__ void y_update(SM& sm, int lane, int r0, int nt) {
 // the prefix, operand layout, written by the prefix kernel) and z_k.
 template <typename T, int NTHR, class SM>
 __device__ __forceinline__ void load_prefix(SM& sm, int tid, int k, int nt, const T* W, const T* zp) {
-  const T* src = W + (int64_t)k * kLargeNTM * 256;
-  for (int e = tid; e < nt * 256; e += NTHR) sm.panel[e] = src[e];
+  const T* src = W + (int64_t)k * kLargeNTM * kOpT;
+  for (int e = tid; e < nt * kOpT; e += NTHR) sm.panel[e] = src[e];
   if (tid < kTile) sm.zk[tid] = zp[kTile * k + tid];
 }
 
@@ -648,9 +650,9 @@ __device__ __forceinline__ void worker_waves_la(SM& sm, int wk, int lane, int nt
       if (tj[s] == k && ti[s] > k) {
         acc_t o = {T(0), T(0), T(0), T(0)};
 #pragma unroll
-        for (int q = 0; q < 4; ++q) o = MF<T>::mma(acc[s][q], sm.negM[64 * q + lane], o);
+        for (int q = 0; q < 4; ++q) o = MF<T>::mma(acc[s][q], sm.negM[68 * q + oplane(lane)], o);
         acc[s] = o;
-        T* P = sm.panel + 256 * ti[s];
+        T* P = sm.panel + kOpT * ti[s];
 #pragma unroll
         for (int t = 0; t < 4; ++t) P[opoff<T>(MF<T>::row(g, t), cl)] = o[t];
       }
@@ -659,11 +661,11 @@ __device__ __forceinline__ void worker_waves_la(SM& sm, int wk, int lane, int nt
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
       if (tj[s] > k) {
-        const T* Pj = sm.panel + 256 * tj[s];
-        const T* Pi = sm.panel + 256 * ti[s];
+        const T* Pj = sm.panel + kOpT * tj[s];
+        const T* Pi = sm.panel + kOpT * ti[s];
         acc_t o = acc[s];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) o = MF<T>::mma(Pj[64 * q + lane], Pi[64 * q + lane], o);
+        for (int q = 0; q < 4; ++q) o = MF<T>::mma(Pj[68 * q + oplane(lane)], Pi[68 * q + oplane(lane)], o);
         acc[s] = o;
         if (ti[s] == k + 1 && tj[s] == k + 1) publish_diag(s, k + 1);
       }
@@ -786,11 +788,11 @@ __device__ __forceinline__ void worker_waves(SM& sm, int wk, int lane, int nt, i
 #pragma unroll
       for (int s = 0; s < SLOTS; ++s) {
         if (tj[s] >= 0) {
-          const T* Pj = sm.panel + 256 * tj[s];
-          const T* Pi = sm.panel + 256 * ti[s];
+          const T* Pj = sm.panel + kOpT * tj[s];
+          const T* Pi = sm.panel + kOpT * ti[s];
           acc_t o = acc[s];
 #pragma unroll
-          for (int q = 0; q < 4; ++q) o = MF<T>::mma(Pj[64 * q + lane], Pi[64 * q + lane], o);
+          for (int q = 0; q < 4; ++q) o = MF<T>::mma(Pj[68 * q + oplane(lane)], Pi[68 * q + oplane(lane)], o);
           acc[s] = o;
         }
       }
@@ -846,9 +848,9 @@ __device__ __forceinline__ void worker_waves(SM& sm, int wk, int lane, int nt, i
       if (tj[s] == k && ti[s] > k) {
         acc_t o = {T(0), T(0), T(0), T(0)};
 #pragma unroll
-        for (int q = 0; q < 4; ++q) o = MF<T>::mma(acc[s][q], sm.negM[64 * q + lane], o);
+        for (int q = 0; q < 4; ++q) o = MF<T>::mma(acc[s][q], sm.negM[68 * q + oplane(lane)], o);
         acc[s] = o;
-        T* P = sm.panel + 256 * ti[s];
+        T* P = sm.panel + kOpT * ti[s];
 #pragma unroll
         for (int t = 0; t < 4; ++t) P[opoff<T>(MF<T>::row(g, t), cl)] = o[t];
       }
@@ -865,11 +867,11 @@ __device__ __forceinline__ void worker_waves(SM& sm, int wk, int lane, int nt, i
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
       if (tj[s] > k) {
-        const T* Pj = sm.panel + 256 * tj[s];
-        const T* Pi = sm.panel + 256 * ti[s];
+        const T* Pj = sm.panel + kOpT * tj[s];
+        const T* Pi = sm.panel + kOpT * ti[s];
         acc_t o = acc[s];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) o = MF<T>::mma(Pj[64 * q + lane], Pi[64 * q + lane], o);
+        for (int q = 0; q < 4; ++q) o = MF<T>::mma(Pj[68 * q + oplane(lane)], Pi[68 * q + oplane(lane)], o);
         acc[s] = o;
       }
     }
@@ -1073,9 +1075,9 @@ template <typename T>
 struct SmemP {
   T z[kLargeNTM * kTile * kMaxDim];  // scaled coordinates: P, then the current chunk of R
   T yv[kLargeNTM * kTile];           // observations of P, overwritten by the forward solve
-  T panel[kLargeNTM * 256];          // generation staging / column k of L (operand layout)
+  T panel[kLargeNTM * kOpT];         // generation staging / column k of L (operand layout)
   T diag[16 * kDiagLd];              // diagonal tile to factor (row-major, padded rows)
-  T negMs[kMaxPrefix * 256];         // -(L_kk^{-T}) of every diagonal tile of P
+  T negMs[kMaxPrefix * kOpT];        // -(L_kk^{-T}) of every diagonal tile of P
   T zk[kTile];
   T xi[1];  // unused: factor_diag's simulation branch is not instantiated here
 };
@@ -1125,7 +1127,7 @@ __device__ __forceinline__ void prefix_panel_wave(SM& sm, int lane, int p, int c
       if (ch == 0) {
         __syncthreads();  // S1: diagonal tile published
         T piv, zr;
-        factor_diag<T>(sm, sm.negMs + 256 * k, lane, k, kTile, diag0, tau, piv, zr, bad, low);
+        factor_diag<T>(sm, sm.negMs + kOpT * k, lane, k, kTile, diag0, tau, piv, zr, bad, low);
         if (lane < kTile) {
           sm.zk[lane] = zr;
           zout[kTile * k + lane] = zr;
@@ -1199,7 +1201,7 @@ __device__ __forceinline__ void prefix_worker_waves(SM& sm, int wk, int lane, in
     }
     for (int k = 0; k < p; ++k) {
       refresh_slots<SLOTS>(ti, tj);
-      const T* nM = sm.negMs + 256 * k;
+      const T* nM = sm.negMs + kOpT * k;
       if (ch == 0) {
 #pragma unroll
         for (int s = 0; s < SLOTS; ++s) {
@@ -1215,7 +1217,7 @@ __device__ __forceinline__ void prefix_worker_waves(SM& sm, int wk, int lane, in
 #pragma unroll
         for (int s = 0; s < SLOTS; ++s) {
           if (tj[s] == k && ti[s] > k && ti[s] < p) {
-            T* P = sm.panel + 256 * ti[s];
+            T* P = sm.panel + kOpT * ti[s];
 #pragma unroll
             for (int t = 0; t < 4; ++t) P[opoff<T>(MF<T>::row(g, t), cl)] = acc[s][t];
           }
@@ -1227,9 +1229,9 @@ __device__ __forceinline__ void prefix_worker_waves(SM& sm, int wk, int lane, in
         if (tj[s] == k && ti[s] < ntl && (ch == 0 ? ti[s] > k : ti[s] >= p)) {
           acc_t o = {T(0), T(0), T(0), T(0)};
 #pragma unroll
-          for (int q = 0; q < 4; ++q) o = MF<T>::mma(acc[s][q], nM[64 * q + lane], o);
+          for (int q = 0; q < 4; ++q) o = MF<T>::mma(acc[s][q], nM[68 * q + oplane(lane)], o);
           acc[s] = o;
-          T* P = sm.panel + 256 * ti[s];
+          T* P = sm.panel + kOpT * ti[s];
 #pragma unroll
           for (int t = 0; t < 4; ++t) P[opoff<T>(MF<T>::row(g, t), cl)] = o[t];
         }
@@ -1237,27 +1239,27 @@ __device__ __forceinline__ void prefix_worker_waves(SM& sm, int wk, int lane, in
       __syncthreads();  // S3: column k of L published
       // L_RP tiles of this chunk to the workspace (contiguous, coalesced)
       {
-        T* dst = Wout + ((int64_t)k * NTM + r0) * 256;
-        const T* src = sm.panel + 256 * p;
-        for (int e = tid - 64; e < cc * 256; e += NTHR - 64) dst[e] = src[e];
+        T* dst = Wout + ((int64_t)k * NTM + r0) * kOpT;
+        const T* src = sm.panel + kOpT * p;
+        for (int e = tid - 64; e < cc * kOpT; e += NTHR - 64) dst[e] = src[e];
       }
       // for the adjoint: column k of L_PP (tile (j, k) at slot k * kMaxPrefix + j,
       // operand layout) and -L_kk^{-T} in the diagonal slot
       if (Lout && ch == 0) {
-        T* dst = Lout + (int64_t)k * kMaxPrefix * 256;
-        for (int e = 256 * k + tid - 64; e < p * 256; e += NTHR - 64)
-          dst[e] = e < 256 * (k + 1) ? sm.negMs[e] : sm.panel[e];
+        T* dst = Lout + (int64_t)k * kMaxPrefix * kOpT;
+        for (int e = kOpT * k + tid - 64; e < p * kOpT; e += NTHR - 64)
+          dst[e] = e < kOpT * (k + 1) ? sm.negMs[e] : sm.panel[e];
       }
       // trailing update restricted to columns of P (the R x R part is left to
       // the register kernel)
 #pragma unroll
       for (int s = 0; s < SLOTS; ++s) {
         if (tj[s] > k && tj[s] < p && ti[s] < ntl && (ch == 0 || ti[s] >= p)) {
-          const T* Pj = sm.panel + 256 * tj[s];
-          const T* Pi = sm.panel + 256 * ti[s];
+          const T* Pj = sm.panel + kOpT * tj[s];
+          const T* Pi = sm.panel + kOpT * ti[s];
           acc_t o = acc[s];
 #pragma unroll
-          for (int q = 0; q < 4; ++q) o = MF<T>::mma(Pj[64 * q + lane], Pi[64 * q + lane], o);
+          for (int q = 0; q < 4; ++q) o = MF<T>::mma(Pj[68 * q + oplane(lane)], Pi[68 * q + oplane(lane)], o);
           acc[s] = o;
         }
       }
@@ -1510,16 +1512,16 @@ __global__ __launch_bounds__(NW * 64) void k_block_prefix_adjoint(const SetDesc*
       // Rhs_P - L_RP^T X_R; workspace tile (k, i) holds L[16p + 16i + a][16k + b] at opoff(a, b)
       for (int e = tid; e < np * kChunk; e += NTHR) {
         const int rr = e / kChunk, c = e - rr * kChunk;
-        const T* Wk = Wp + (int64_t)(rr >> 4) * kLargeNTM * 256;
+        const T* Wk = Wp + (int64_t)(rr >> 4) * kLargeNTM * kOpT;
         const int cc = rr & 15;
         T acc = T(0);
-        for (int r = 0; r < nR; ++r) acc += Wk[(r >> 4) * 256 + opoff<T>(r & 15, cc)] * sm.xr[r * kRS + c];
+        for (int r = 0; r < nR; ++r) acc += Wk[(r >> 4) * kOpT + opoff<T>(r & 15, cc)] * sm.xr[r * kRS + c];
         sm.rp[rr * kRS + c] = (c0 + c == 0 ? zp[rr] : T(0)) - acc;
       }
       __syncthreads();
       for (int k = p - 1; k >= 0; --k) {
         // X_k = L_kk^{-T} Rhs_k; the diagonal slot holds -(L_kk^{-1})[a][b] at opoff(a, b)
-        const T* nM = Lp + ((int64_t)k * kMaxPrefix + k) * 256;
+        const T* nM = Lp + ((int64_t)k * kMaxPrefix + k) * kOpT;
         for (int e = tid; e < kTile * kChunk; e += NTHR) {
           const int a = e / kChunk, c = e - a * kChunk;
           T acc = T(0);
@@ -1534,7 +1536,7 @@ __global__ __launch_bounds__(NW * 64) void k_block_prefix_adjoint(const SetDesc*
         // Rhs_j -= L_kj^T X_k for j < k; tile (k, j) sits in slot j * kMaxPrefix + k
         for (int e = tid; e < kTile * k * kChunk; e += NTHR) {
           const int rr = e / kChunk, c = e - rr * kChunk;
-          const T* Lkj = Lp + ((int64_t)(rr >> 4) * kMaxPrefix + k) * 256;
+          const T* Lkj = Lp + ((int64_t)(rr >> 4) * kMaxPrefix + k) * kOpT;
           const int b = rr & 15;
           T acc = T(0);
           for (int a = 0; a < kTile; ++a) acc += Lkj[opoff<T>(a, b)] * sm.xk[a * kRS + c];

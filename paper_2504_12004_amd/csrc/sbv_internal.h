@@ -52,10 +52,14 @@ struct Variant {
 // their part of z to a workspace; the trailing kLargeNTM tiles are then
 // factored by the register kernel after p streamed rank-16 updates.
 constexpr int kLargeNTM = 17;
+// Elements of one 16x16 tile in the MFMA operand layout (the three padding
+// elements per 16-row group keep the layout change of the column solves free
+// of LDS bank conflicts).
+constexpr int kOpT = 272;
 constexpr int kMaxPrefix = 15;  // joint sizes up to 16 * (kLargeNTM + kMaxPrefix) = 512
-constexpr int64_t kLargeW = (int64_t)kMaxPrefix * kLargeNTM * 256;  // panel elements per workspace slot
+constexpr int64_t kLargeW = (int64_t)kMaxPrefix * kLargeNTM * kOpT;  // panel elements per workspace slot
 constexpr int64_t kLargeZ = (int64_t)kMaxPrefix * kTile;            // z elements per workspace slot
-constexpr int64_t kLargeL = (int64_t)kMaxPrefix * kMaxPrefix * 256;  // L_PP elements per slot (gradient)
+constexpr int64_t kLargeL = (int64_t)kMaxPrefix * kMaxPrefix * kOpT;  // L_PP elements per slot (gradient)
 
 // Workspace window of one launch of the large-block kernels: they process
 // items[off + i] for i < min(*count - off, nb), item i using workspace slot i
