@@ -203,10 +203,30 @@ __device__ __forceinline__ unsigned row_all_u(unsigned x, int gj) {
   const auto b = __builtin_amdgcn_permlane32_swap(e, e, false, false);   // lower / upper half doubled
   return (gj & 2) ? b[1] : b[0];
 }
+// FP64: one 64-bit DPP move (v_mov_b64 row_newbcast, checked on the device)
+template <int J>
+__device__ __forceinline__ double nb_d(double v) {
+  return __builtin_amdgcn_update_dpp(v, v, 0x150 + J, 0xf, 0xf, false);
+}
 __device__ __forceinline__ double row_lane(double v, int j) {
-  const unsigned long long u = (unsigned long long)__double_as_longlong(v);
-  const unsigned lo = row_lane_u((unsigned)u, j), hi = row_lane_u((unsigned)(u >> 32), j);
-  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+  switch (j) {
+    case 0: return nb_d<0>(v);
+    case 1: return nb_d<1>(v);
+    case 2: return nb_d<2>(v);
+    case 3: return nb_d<3>(v);
+    case 4: return nb_d<4>(v);
+    case 5: return nb_d<5>(v);
+    case 6: return nb_d<6>(v);
+    case 7: return nb_d<7>(v);
+    case 8: return nb_d<8>(v);
+    case 9: return nb_d<9>(v);
+    case 10: return nb_d<10>(v);
+    case 11: return nb_d<11>(v);
+    case 12: return nb_d<12>(v);
+    case 13: return nb_d<13>(v);
+    case 14: return nb_d<14>(v);
+    default: return nb_d<15>(v);
+  }
 }
 __device__ __forceinline__ float row_lane(float v, int j) { return __uint_as_float(row_lane_u(__float_as_uint(v), j)); }
 __device__ __forceinline__ double row_all(double v, int gj) {
@@ -482,7 +502,11 @@ __device__ __forceinline__ void panel_wave(SM& sm, int lane, int nt, int mi, int
     __syncthreads();  // S1: diagonal tile published
     SBV_PROF(1, true);
     T piv, zr, ysim = T(0);
+    // the serial diagonal factorisations are the critical path: they win issue
+    // arbitration against the worker that shares this SIMD
+    __builtin_amdgcn_s_setprio(2);
     factor_diag<T, SAMPLE>(sm, sm.negM, lane, k, nA - kTile * k, diag0, tau, piv, zr, bad, low, mi, &ysim);
+    __builtin_amdgcn_s_setprio(0);
     const int rowg = kTile * k + lane;
     if (SAMPLE && lane < 16 && rowg >= mi && rowg < nA) yout[rowg - mi] = (double)ysim;
     if (lane < 16) {
@@ -538,7 +562,9 @@ __device__ __forceinline__ void panel_wave_la(SM& sm, int lane, int nt, int mi, 
   auto factor_step = [&](int k) {
     while (__atomic_load_n(&sm.la_flag, __ATOMIC_ACQUIRE) < k) __builtin_amdgcn_s_sleep(1);
     T piv, zr;
+    __builtin_amdgcn_s_setprio(2);
     factor_diag<T>(sm, sm.negM, lane, k, nA - kTile * k, diag0, tau, piv, zr, bad, low);
+    __builtin_amdgcn_s_setprio(0);
     const int rowg = kTile * k + lane;
     if (lane < 16) {
       sm.zk[lane] = zr;
@@ -595,7 +621,8 @@ __device__ __forceinline__ void worker_waves_la(SM& sm, int wk, int lane, int nt
   // of the diagonal tile j; columns 0 and 1 are staged up front.  FP32
   // generates every column first (see worker_waves).
   T* stage = sm.panel + Smem<T, NTM, false>::kPanel;
-  const int wtid = 64 * wk + lane;
+  const int wrank = wk == 3 ? NWK - 1 : (wk > 3 ? wk - 1 : wk);  // wave 4 last, as above
+  const int wtid = 64 * wrank + lane;
   auto add_staged = [&](int j) {
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
@@ -802,7 +829,10 @@ __device__ __forceinline__ void worker_waves(SM& sm, int wk, int lane, int nt, i
   // covariance column j is staged by the workers in the second half of the
   // panel (`stage`) and added by the owners of its tiles
   T* stage = sm.panel + Smem<T, NTM, GRAD>::kPanel;
-  const int wtid = 64 * wk + lane;
+  // generation work goes to worker 3 (wave 4, which shares its SIMD with the
+  // panel wave's diagonal factorisations) last
+  const int wrank = wk == 3 ? NWK - 1 : (wk > 3 ? wk - 1 : wk);
+  const int wtid = 64 * wrank + lane;
   if (kLateCov<T>) {
     gen_column<T, NTHR - 64>(sm, stage, wtid, 0, 0, nt, nA, d, two_nu, sigma2, tau2);
     __syncthreads();  // G0: covariance column 0 staged
