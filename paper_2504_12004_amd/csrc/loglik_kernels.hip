@@ -136,12 +136,14 @@ template <typename T, int NTM, bool GRAD = false>
 struct Smem {
   static constexpr int kPanel = NTM * kOpT;
   static constexpr int kRhs = NTM * kTile * kRS;
+  static constexpr int kPanelElems = (GRAD && kRhs > 2 * kPanel) ? kRhs : 2 * kPanel;
+  static constexpr int kStageTiles = kPanelElems / 256;  // staged covariance tiles that fit the panel
   T z[NTM * kTile * kMaxDim];  // scaled coordinates of A (padded rows unused)
   T yv[NTM * kTile];           // observations, overwritten by the forward solve
   // column k of L in operand layout (factorisation); its second half stages
   // the next covariance column; right-hand-side chunk of the adjoint solves
   // (GRAD only)
-  T panel[(GRAD && kRhs > 2 * kPanel) ? kRhs : 2 * kPanel];
+  T panel[kPanelElems];
   T diag[16 * kDiagLd];        // diagonal tile to factor (row-major, padded rows)
   T negM[kOpT];                // -(L_kk^{-T}) in B-operand layout
   T zk[kTile];                 // solved z of the current tile row
@@ -426,6 +428,88 @@ __device__ __forceinline__ void gen_column(SM& sm, T* dst, int tid, int j, int i
   }
 }
 
+// Covariance tiles (i, j) of the columns j0 <= j < j1 (i >= j), numbered
+// column by column from 0 and staged at dst + 256 u in the same per-tile order
+// as gen_column; two work items per thread in flight.
+template <typename T, class SM>
+__device__ __forceinline__ void group_tile(int u, int j0, int nt, int& i, int& j) {
+  j = j0;
+  while (u >= nt - j) {
+    u -= nt - j;
+    ++j;
+  }
+  i = j + u;
+}
+template <typename T, int NTHR, class SM>
+__device__ __forceinline__ void gen_group(SM& sm, T* dst, int tid, int j0, int j1, int nt, int nA, int d, int two_nu,
+                                         T sigma2, T tau2) {
+  int tiles = 0;
+  for (int j = j0; j < j1; ++j) tiles += nt - j;
+  const int total = 64 * tiles;
+  auto one = [&](int e, T (&v)[4], int& u, int& l) {
+    int i, j;
+    u = e >> 6;
+    l = e & 63;
+    group_tile<T, SM>(u, j0, nt, i, j);
+    const int pb = kTile * i + (l & 15);
+    const int pbc = pb < nA ? pb : 0;
+    int pa[4], pac[4];
+    T r2[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      pa[t] = kTile * j + MF<T>::row(l >> 4, t);
+      pac[t] = pa[t] < nA ? pa[t] : 0;
+      r2[t] = T(0);
+    }
+    for (int k = 0; k < d; ++k) {
+      const T zbk = sm.z[pbc * d + k];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const T df = sm.z[pac[t] * d + k] - zbk;
+        r2[t] += df * df;
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      if (pa[t] >= nA || pb >= nA) {
+        v[t] = (pa[t] == pb) ? T(-1) : T(0);
+      } else {
+        v[t] = -(sigma2 * matern<T>(t_sqrt(r2[t]), two_nu));
+        if (pa[t] == pb) v[t] -= tau2;
+      }
+    }
+  };
+  int e = tid;
+  for (; e + NTHR < total; e += 2 * NTHR) {
+    T v0[4], v1[4];
+    int u0, l0, u1, l1;
+    one(e, v0, u0, l0);
+    one(e + NTHR, v1, u1, l1);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      dst[256 * u0 + 64 * t + l0] = v0[t];
+      dst[256 * u1 + 64 * t + l1] = v1[t];
+    }
+  }
+  if (e < total) {
+    T v0[4];
+    int u0, l0;
+    one(e, v0, u0, l0);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) dst[256 * u0 + 64 * t + l0] = v0[t];
+  }
+}
+
+// Next group of whole columns [j0, j1) whose tiles fit `cap` staged tiles.
+__device__ __forceinline__ int group_end(int j0, int nt, int cap) {
+  int j1 = j0, tiles = 0;
+  while (j1 < nt && tiles + (nt - j1) <= cap) {
+    tiles += nt - j1;
+    ++j1;
+  }
+  return j1 > j0 ? j1 : j0 + 1;
+}
+
 // Forward-solve update of the observations in rows r0..r1-1 with the column
 // tile of L staged in the panel: y_rho -= L[rho][16k..16k+15] z_k, four rows
 // per lane as independent chains (y_update: rows r0..16nt-1 with z_k from LDS).
@@ -481,10 +565,12 @@ __device__ __forceinline__ void panel_wave(SM& sm, int lane, int nt, int mi, int
   const T diag0 = sigma2 + tau2;
   SBV_PROF_DECL
   if (!kLateCov<T>) {
-    for (int j = 0; j < nt; ++j) {
-      gen_column<T, NTHR>(sm, sm.panel, lane, j, j, nt, nA, d, two_nu, sigma2, tau2);
+    for (int j0 = 0; j0 < nt;) {
+      const int j1 = group_end(j0, nt, Smem<T, NTM, GRAD>::kStageTiles);
+      gen_group<T, NTHR>(sm, sm.panel, lane, j0, j1, nt, nA, d, two_nu, sigma2, tau2);
       __syncthreads();  // G1
       __syncthreads();  // G2
+      j0 = j1;
     }
   }
   if (PRE) {
@@ -553,10 +639,12 @@ __device__ __forceinline__ void panel_wave_la(SM& sm, int lane, int nt, int mi, 
     __syncthreads();  // Ga: covariance column 0 staged
     __syncthreads();  // Gb: column 0 added, diagonal tile 0 published
   } else {
-    for (int j = 0; j < nt; ++j) {
-      gen_column<T, NTHR>(sm, sm.panel, lane, j, j, nt, nA, d, two_nu, sigma2, tau2);
+    for (int j0 = 0; j0 < nt;) {
+      const int j1 = group_end(j0, nt, Smem<T, NTM, false>::kStageTiles);
+      gen_group<T, NTHR>(sm, sm.panel, lane, j0, j1, nt, nA, d, two_nu, sigma2, tau2);
       __syncthreads();  // G1
       __syncthreads();  // G2
+      j0 = j1;
     }
   }
   auto factor_step = [&](int k) {
@@ -639,19 +727,22 @@ __device__ __forceinline__ void worker_waves_la(SM& sm, int wk, int lane, int nt
     refresh_slots<SLOTS>(ti, tj);
     add_staged(0);
   } else {
-    for (int j = 0; j < nt; ++j) {
+    for (int j0 = 0; j0 < nt;) {
+      const int j1 = group_end(j0, nt, Smem<T, NTM, false>::kStageTiles);
       refresh_slots<SLOTS>(ti, tj);
-      gen_column<T, NTHR>(sm, sm.panel, 64 * (wk + 1) + lane, j, j, nt, nA, d, two_nu, sigma2, tau2);
+      gen_group<T, NTHR>(sm, sm.panel, 64 * (wk + 1) + lane, j0, j1, nt, nA, d, two_nu, sigma2, tau2);
       __syncthreads();  // G1
 #pragma unroll
       for (int s = 0; s < SLOTS; ++s) {
-        if (tj[s] == j) {
-          const T* src = sm.panel + 256 * ti[s];
+        if (tj[s] >= j0 && tj[s] < j1) {
+          const int u = (tj[s] - j0) * nt - (tj[s] * (tj[s] - 1) - j0 * (j0 - 1)) / 2 + (ti[s] - tj[s]);
+          const T* src = sm.panel + 256 * u;
 #pragma unroll
           for (int t = 0; t < 4; ++t) acc[s][t] = src[64 * t + lane];
         }
       }
       __syncthreads();  // G2
+      j0 = j1;
     }
   }
   auto publish_diag = [&](int s, int k) {
@@ -790,20 +881,25 @@ __device__ __forceinline__ void worker_waves(SM& sm, int wk, int lane, int nt, i
   }
   SBV_PROF_DECL
   if (!kLateCov<T>) {
-    // every thread of the workgroup builds a column into LDS, owners copy theirs in
-    for (int j = 0; j < nt; ++j) {
+    // every thread of the workgroup builds groups of whole columns into LDS,
+    // owners copy theirs in
+    for (int j0 = 0; j0 < nt;) {
+      const int j1 = group_end(j0, nt, Smem<T, NTM, GRAD>::kStageTiles);
       refresh_slots<SLOTS>(ti, tj);
-      gen_column<T, NTHR>(sm, sm.panel, 64 * (wk + 1) + lane, j, j, nt, nA, d, two_nu, sigma2, tau2);
-      __syncthreads();  // G1: column j staged
+      gen_group<T, NTHR>(sm, sm.panel, 64 * (wk + 1) + lane, j0, j1, nt, nA, d, two_nu, sigma2, tau2);
+      __syncthreads();  // G1: columns j0..j1-1 staged
 #pragma unroll
       for (int s = 0; s < SLOTS; ++s) {
-        if (tj[s] == j) {
-          const T* src = sm.panel + 256 * ti[s];
+        if (tj[s] >= j0 && tj[s] < j1) {
+          // tiles before column tj[s] in the group: sum_{j=j0}^{tj-1} (nt - j)
+          const int u = (tj[s] - j0) * nt - (tj[s] * (tj[s] - 1) - j0 * (j0 - 1)) / 2 + (ti[s] - tj[s]);
+          const T* src = sm.panel + 256 * u;
 #pragma unroll
           for (int t = 0; t < 4; ++t) acc[s][t] = src[64 * t + lane];
         }
       }
       __syncthreads();  // G2: staging area free
+      j0 = j1;
     }
   }
   if (PRE) {
