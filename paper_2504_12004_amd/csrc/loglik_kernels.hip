@@ -85,6 +85,26 @@ __device__ __forceinline__ float t_exp(float x) { return expf(x); }
 __device__ __forceinline__ double t_sqrt(double x) { return sqrt(x); }
 __device__ __forceinline__ float t_sqrt(float x) { return sqrtf(x); }
 
+// Scaled coordinates in LDS: one row of zld(d) elements per point (d rounded
+// up to 16 bytes, zero padded), so that the covariance generation reads them
+// as 16-byte vectors.
+template <typename T>
+struct ZV;
+template <>
+struct ZV<double> {
+  typedef double v __attribute__((ext_vector_type(2)));
+  static constexpr int w = 2;
+};
+template <>
+struct ZV<float> {
+  typedef float v __attribute__((ext_vector_type(4)));
+  static constexpr int w = 4;
+};
+template <typename T>
+__device__ __forceinline__ int zld(int d) {
+  return (d + ZV<T>::w - 1) / ZV<T>::w * ZV<T>::w;
+}
+
 // Matern correlation, closed forms of Eq. (maternkernel) for half-integer nu.
 template <typename T>
 __device__ __forceinline__ T matern(T r, int two_nu) {
@@ -138,7 +158,7 @@ struct Smem {
   static constexpr int kRhs = NTM * kTile * kRS;
   static constexpr int kPanelElems = (GRAD && kRhs > 2 * kPanel) ? kRhs : 2 * kPanel;
   static constexpr int kStageTiles = kPanelElems / 256;  // staged covariance tiles that fit the panel
-  T z[NTM * kTile * kMaxDim];  // scaled coordinates of A (padded rows unused)
+  alignas(16) T z[NTM * kTile * kMaxDim];  // scaled coordinates of A, rows of zld(d)
   T yv[NTM * kTile];           // observations, overwritten by the forward solve
   // column k of L in operand layout (factorisation); its second half stages
   // the next covariance column; right-hand-side chunk of the adjoint solves
@@ -383,14 +403,17 @@ __device__ __forceinline__ void gen_items(SM& sm, T* dst, const int (&e)[N], int
       r2[n][t] = T(0);
     }
   }
-  for (int k = 0; k < d; ++k) {
+  typedef typename ZV<T>::v zv;
+  const int ld = zld<T>(d);
+  for (int k = 0; k < ld; k += ZV<T>::w) {
 #pragma unroll
     for (int n = 0; n < N; ++n) {
-      const T zbk = sm.z[pbc[n] * d + k];
+      const zv zb = *reinterpret_cast<const zv*>(sm.z + pbc[n] * ld + k);
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
-        const T df = sm.z[pac[n][t] * d + k] - zbk;
-        r2[n][t] += df * df;
+        const zv df = *reinterpret_cast<const zv*>(sm.z + pac[n][t] * ld + k) - zb;
+#pragma unroll
+        for (int c = 0; c < ZV<T>::w; ++c) r2[n][t] += df[c] * df[c];
       }
     }
   }
@@ -461,12 +484,15 @@ __device__ __forceinline__ void gen_group(SM& sm, T* dst, int tid, int j0, int j
       pac[t] = pa[t] < nA ? pa[t] : 0;
       r2[t] = T(0);
     }
-    for (int k = 0; k < d; ++k) {
-      const T zbk = sm.z[pbc * d + k];
+    typedef typename ZV<T>::v zv;
+    const int ld = zld<T>(d);
+    for (int k = 0; k < ld; k += ZV<T>::w) {
+      const zv zb = *reinterpret_cast<const zv*>(sm.z + pbc * ld + k);
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
-        const T df = sm.z[pac[t] * d + k] - zbk;
-        r2[t] += df * df;
+        const zv df = *reinterpret_cast<const zv*>(sm.z + pac[t] * ld + k) - zb;
+#pragma unroll
+        for (int c = 0; c < ZV<T>::w; ++c) r2[t] += df[c] * df[c];
       }
     }
 #pragma unroll
@@ -1126,11 +1152,12 @@ __global__ __launch_bounds__(NW * 64) void k_block_loglik(const SetDesc* __restr
     const T* zp = PRE ? reinterpret_cast<const T*>(L.z) + (int64_t)it * kLargeZ : nullptr;
 
     // gather A = J u B (J first): scaled coordinates and observations
-    for (int e = tid; e < nAl * d; e += NW * 64) {
-      int pl = e / d, k = e - pl * d;
+    const int ld = zld<T>(d);
+    for (int e = tid; e < nAl * ld; e += NW * 64) {
+      int pl = e / ld, k = e - pl * ld;
       int pa = pl + off;
       int pos = pa < mi ? S.nidx[n0 + pa] : b0 + (pa - mi);
-      sm.z[pl * d + k] = T(S.X[(int64_t)pos * d + k] * exp(-th[k]));
+      sm.z[pl * ld + k] = k < d ? T(S.X[(int64_t)pos * d + k] * exp(-th[k])) : T(0);
     }
     for (int pl = tid; pl < nt * kTile; pl += NW * 64) {
       const int pa = pl + off;
@@ -1199,7 +1226,7 @@ __global__ __launch_bounds__(NW * 64) void k_block_loglik(const SetDesc* __restr
 // z_P beside it; k_block_loglik<..., PRE> consumes both.
 template <typename T>
 struct SmemP {
-  T z[kLargeNTM * kTile * kMaxDim];  // scaled coordinates: P, then the current chunk of R
+  alignas(16) T z[kLargeNTM * kTile * kMaxDim];  // scaled coordinates (rows of zld(d)): P, then a chunk of R
   T yv[kLargeNTM * kTile];           // observations of P, overwritten by the forward solve
   T panel[kLargeNTM * kOpT];         // generation staging / column k of L (operand layout)
   T diag[16 * kDiagLd];              // diagonal tile to factor (row-major, padded rows)
@@ -1213,15 +1240,16 @@ struct SmemP {
 template <typename T, int NTHR>
 __device__ __forceinline__ void gather_points(T* z, T* yv, int tid, int lo, int hi, int shift, int d, int mi,
                                               int nA, const SetDesc& S, int b0, int64_t n0, const double* th) {
-  for (int e = tid; e < (hi - lo) * d; e += NTHR) {
-    const int pl = lo + e / d, k = e % d;
+  const int ld = zld<T>(d);
+  for (int e = tid; e < (hi - lo) * ld; e += NTHR) {
+    const int pl = lo + e / ld, k = e % ld;
     const int pa = pl + shift;
     T v = T(0);
-    if (pa < nA) {
+    if (pa < nA && k < d) {
       const int pos = pa < mi ? S.nidx[n0 + pa] : b0 + (pa - mi);
       v = T(S.X[(int64_t)pos * d + k] * exp(-th[k]));
     }
-    z[pl * d + k] = v;
+    z[pl * ld + k] = v;
   }
   if (yv)
     for (int pl = lo + tid; pl < hi; pl += NTHR) {
