@@ -100,10 +100,12 @@ def main():
     torch.cuda.synchronize()
 
     # per size bucket, pick the fastest kernel variant and schedule (setup, not timed)
-    tuned = {}
+    tuned, sched = {}, {}
     for name, prec in (("fp64", sbv.SBV_FP64), ("fp32", sbv.SBV_FP32)):
-        tuned[name] = [int(t) for t in sbv.sbv_autotune([B], theta_true, two_nu, prec, reps=3)]
-    log(f"autotuned tiles per bucket: {tuned}")
+        ch, la = sbv.sbv_autotune([B], theta_true, two_nu, prec, reps=3, with_schedule=True)
+        tuned[name] = [int(t) for t in ch]
+        sched[name] = ["lookahead" if x else "plain" for x in la]
+    log(f"autotuned tiles per bucket: {tuned}, schedules {sched}")
 
     thetas = synth.perturbed_thetas(theta_true, w["n_theta"], w["theta_seed"])
     th_d = torch.tensor(thetas, dtype=torch.float64, device=dev)
@@ -203,6 +205,7 @@ def main():
             "grad_fp64_evals_per_s": grad_rate,
             "build_seconds": t_build,
             "autotuned_tiles": tuned,
+            "autotuned_schedules": sched,
             "fits": fits,
             "m400_5m": large,
         },

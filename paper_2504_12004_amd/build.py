@@ -3,7 +3,7 @@
 Every HIP source is compiled for gfx950 with packed FP32 instructions disabled
 (`-Xclang -target-feature -Xclang -packed-fp32-ops`), then linked into one
 shared library next to this file.  Object files are cached by content hash
-under _build/ so an unchanged source is not recompiled.
+under _build/ so an unchanged source is not recompiled, unless force=True.
 """
 import hashlib
 import os
@@ -38,10 +38,10 @@ def _hash(path):
     return h.hexdigest()[:16]
 
 
-def _compile(src, verbose):
+def _compile(src, verbose, force=False):
     path = os.path.join(CSRC, src)
     obj = os.path.join(BUILD, f"{src}.{_hash(path)}.o")
-    if os.path.exists(obj):
+    if os.path.exists(obj) and not force:
         return obj
     lang = ["-x", "hip"] if src.endswith(".hip") else []
     cmd = [HIPCC] + FLAGS + lang + ["-c", path, "-o", obj + ".tmp"]
@@ -55,11 +55,11 @@ def _compile(src, verbose):
     return obj
 
 
-def build(verbose=False, jobs=8):
+def build(verbose=False, jobs=8, force=False):
     os.makedirs(BUILD, exist_ok=True)
     srcs = _sources()
     with ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(lambda s: _compile(s, verbose), srcs))
+        objs = list(ex.map(lambda s: _compile(s, verbose, force), srcs))
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", LIB + ".tmp"] + objs
     if verbose:
         print(" ".join(cmd), flush=True)

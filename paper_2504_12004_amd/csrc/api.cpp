@@ -693,7 +693,7 @@ sbv_status sbv_sample(sbv_blocks h, const double* theta, int32_t two_nu, const d
 // ---- autotuner: per size bucket, time every kernel variant that can hold the
 // bucket's largest joint size and keep the fastest.
 sbv_status sbv_autotune(const sbv_blocks* sets, int32_t n_sets, const int32_t* two_nu, const double* theta,
-                        int32_t prec, int32_t reps, int32_t* chosen_tiles) {
+                        int32_t prec, int32_t reps, int32_t* chosen_tiles, int32_t* chosen_lookahead) {
   sbv_status st = check_sets(sets, n_sets, two_nu);
   if (st) return st;
   if (!theta || reps <= 0) return fail(SBV_E_INVAL, "theta and reps > 0 are required");
@@ -709,6 +709,7 @@ sbv_status sbv_autotune(const sbv_blocks* sets, int32_t n_sets, const int32_t* t
   for (auto& B : P->buckets) {
     if (B.large) {  // one kernel pair, nothing to choose
       if (chosen_tiles) chosen_tiles[bi] = kLargeNTM + kMaxPrefix;
+      if (chosen_lookahead) chosen_lookahead[bi] = 0;
       ++bi;
       continue;
     }
@@ -738,6 +739,7 @@ sbv_status sbv_autotune(const sbv_blocks* sets, int32_t n_sets, const int32_t* t
     B.tuned[pk] = bestv;
     B.la[pk] = bestla;
     if (chosen_tiles) chosen_tiles[bi] = variant(bestv).ntm;
+    if (chosen_lookahead) chosen_lookahead[bi] = bestla ? 1 : 0;
     ++bi;
   }
   (void)hipEventDestroy(a);

@@ -152,21 +152,22 @@ constexpr int kChunk = 32;
 template <typename T>
 constexpr bool kLateCov = sizeof(T) == 8;
 
-template <typename T, int NTM, bool GRAD = false>
+template <typename T, int NTM, bool GRAD = false, bool LA = false>
 struct Smem {
   static constexpr int kPanel = NTM * kOpT;
   static constexpr int kRhs = NTM * kTile * kRS;
-  static constexpr int kPanelElems = (GRAD && kRhs > 2 * kPanel) ? kRhs : 2 * kPanel;
+  // lookahead: two column buffers (steps alternate) before the stage
+  static constexpr int kPanelElems = LA ? 3 * kPanel : (GRAD && kRhs > 2 * kPanel) ? kRhs : 2 * kPanel;
   static constexpr int kStageTiles = kPanelElems / 256;  // staged covariance tiles that fit the panel
   alignas(16) T z[NTM * kTile * kMaxDim];  // scaled coordinates of A, rows of zld(d)
   T yv[NTM * kTile];           // observations, overwritten by the forward solve
-  // column k of L in operand layout (factorisation); its second half stages
-  // the next covariance column; right-hand-side chunk of the adjoint solves
-  // (GRAD only)
+  // column k of L in operand layout (factorisation; lookahead: columns k and
+  // k-1, in buffers k&1); the part after it stages the next covariance
+  // column; right-hand-side chunk of the adjoint solves (GRAD only)
   T panel[kPanelElems];
   T diag[16 * kDiagLd];        // diagonal tile to factor (row-major, padded rows)
   T negM[kOpT];                // -(L_kk^{-T}) in B-operand layout
-  T zk[kTile];                 // solved z of the current tile row
+  T zk[2 * kTile];             // solved z of the current tile row (lookahead: of rows k and k-1)
   T zfull[GRAD ? NTM * kTile : 1];  // all of z = L^{-1} y (GRAD only)
   T xi[NTM * kTile];                // innovations of the conditional simulator
   int la_flag;                      // lookahead: last diagonal step published
@@ -540,7 +541,7 @@ __device__ __forceinline__ int group_end(int j0, int nt, int cap) {
 // tile of L staged in the panel: y_rho -= L[rho][16k..16k+15] z_k, four rows
 // per lane as independent chains (y_update: rows r0..16nt-1 with z_k from LDS).
 template <typename T, class SM>
-__device__ __forceinline__ void y_update_rows(SM& sm, int lane, int r0, int r1, const T (&zk)[16]) {
+__device__ __forceinline__ void y_update_rows(SM& sm, const T* P, int lane, int r0, int r1, const T (&zk)[16]) {
   for (int base = r0; base < r1; base += 256) {
     T v[4];
     int rho[4];
@@ -554,7 +555,7 @@ __device__ __forceinline__ void y_update_rows(SM& sm, int lane, int r0, int r1, 
 #pragma unroll
       for (int it = 0; it < 4; ++it) {
         const int rr = rho[it] < r1 ? rho[it] : r0;
-        v[it] -= sm.panel[kOpT * (rr >> 4) + opoff<T>(rr & 15, c)] * zk[c];
+        v[it] -= P[kOpT * (rr >> 4) + opoff<T>(rr & 15, c)] * zk[c];
       }
     }
 #pragma unroll
@@ -567,7 +568,28 @@ __device__ __forceinline__ void y_update(SM& sm, int lane, int r0, int nt) {
   T zk[16];
 #pragma unroll
   for (int c = 0; c < 16; ++c) zk[c] = sm.zk[c];
-  y_update_rows<T>(sm, lane, r0, kTile * nt, zk);
+  y_update_rows<T>(sm, sm.panel, lane, r0, kTile * nt, zk);
+}
+// Rows r0..r1-1 with the column in panel buffer b and z from zk buffer b
+// (lookahead schedule).
+template <typename T, int KP, class SM>
+__device__ __forceinline__ void y_update_buf(SM& sm, int b, int lane, int r0, int r1) {
+  T zk[16];
+#pragma unroll
+  for (int c = 0; c < 16; ++c) zk[c] = sm.zk[kTile * b + c];
+  y_update_rows<T>(sm, sm.panel + KP * b, lane, r0, r1, zk);
+}
+// The 16 rows of tile kt only: lane (r, g) sums columns 4g..4g+3 of row r,
+// rows_sum adds the four partial sums.
+template <typename T, int KP, class SM>
+__device__ __forceinline__ void y_update_tile(SM& sm, int b, int lane, int kt) {
+  const int r = lane & 15, g = lane >> 4;
+  const T* P = sm.panel + KP * b + kOpT * kt;
+  T part = T(0);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) part += P[opoff<T>(r, 4 * g + q)] * sm.zk[kTile * b + 4 * g + q];
+  const T sum = rows_sum(part);
+  if (g == 0) sm.yv[kTile * kt + r] -= sum;
 }
 
 // Stage column tile k of a large block's prefix panel (nt tiles of L below
@@ -661,41 +683,56 @@ template <typename T, int NTM, int NTHR, class SM>
 __device__ __forceinline__ void panel_wave_la(SM& sm, int lane, int nt, int mi, int nA, int d, int two_nu, T sigma2, T tau2, T tau,
                               double& ld_acc, double& q_acc, int& bad, int& low) {
   const T diag0 = sigma2 + tau2;
+  SBV_PROF_DECL
   if (kLateCov<T>) {
     __syncthreads();  // Ga: covariance column 0 staged
     __syncthreads();  // Gb: column 0 added, diagonal tile 0 published
   } else {
     for (int j0 = 0; j0 < nt;) {
-      const int j1 = group_end(j0, nt, Smem<T, NTM, false>::kStageTiles);
+      const int j1 = group_end(j0, nt, Smem<T, NTM, false, true>::kStageTiles);
       gen_group<T, NTHR>(sm, sm.panel, lane, j0, j1, nt, nA, d, two_nu, sigma2, tau2);
       __syncthreads();  // G1
       __syncthreads();  // G2
       j0 = j1;
     }
   }
+  constexpr int KP = Smem<T, NTM, false, true>::kPanel;
   auto factor_step = [&](int k) {
     while (__atomic_load_n(&sm.la_flag, __ATOMIC_ACQUIRE) < k) __builtin_amdgcn_s_sleep(1);
+    SBV_PROF(3, true);
     T piv, zr;
     __builtin_amdgcn_s_setprio(2);
     factor_diag<T>(sm, sm.negM, lane, k, nA - kTile * k, diag0, tau, piv, zr, bad, low);
     __builtin_amdgcn_s_setprio(0);
     const int rowg = kTile * k + lane;
     if (lane < 16) {
-      sm.zk[lane] = zr;
+      sm.zk[kTile * (k & 1) + lane] = zr;
       if (rowg >= mi && rowg < nA) {
         ld_acc += log((double)piv);
         q_acc += (double)zr * (double)zr;
       }
     }
+    SBV_PROF(4, true);
   };
+  SBV_PROF(0, true);
   factor_step(0);
   __syncthreads();  // P0: step 0 factored
+  SBV_PROF(5, true);
+  // The forward-solve update of column k is split: the rows of tile k+1 go
+  // right after S3 (factor k+1 needs them), the rows below after S4, from the
+  // other column buffer, while the workers solve column k+1.
   for (int k = 0; k < nt; ++k) {
+    if (k >= 1) y_update_buf<T, KP>(sm, (k - 1) & 1, lane, kTile * (k + 1), kTile * nt);
+    SBV_PROF(2, true);
     __syncthreads();  // S3: column k of L published
-    // (the y update overlaps the wait for diagonal tile k+1)
-    y_update<T>(sm, lane, kTile * (k + 1), nt);
-    if (k + 1 < nt) factor_step(k + 1);
+    SBV_PROF(1, true);
+    if (k + 1 < nt) {
+      y_update_tile<T, KP>(sm, k & 1, lane, k + 1);
+      SBV_PROF(2, true);
+      factor_step(k + 1);
+    }
     __syncthreads();  // S4: trailing update and next diagonal done
+    SBV_PROF(5, true);
   }
 }
 
@@ -734,9 +771,11 @@ __device__ __forceinline__ void worker_waves_la(SM& sm, int wk, int lane, int nt
   // the start of step j-1, before that step's update and early publication
   // of the diagonal tile j; columns 0 and 1 are staged up front.  FP32
   // generates every column first (see worker_waves).
-  T* stage = sm.panel + Smem<T, NTM, false>::kPanel;
+  constexpr int KP = Smem<T, NTM, false, true>::kPanel;
+  T* stage = sm.panel + 2 * KP;
   const int wrank = wk == 3 ? NWK - 1 : (wk > 3 ? wk - 1 : wk);  // wave 4 last, as above
   const int wtid = 64 * wrank + lane;
+  SBV_PROF_DECL
   auto add_staged = [&](int j) {
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
@@ -754,7 +793,7 @@ __device__ __forceinline__ void worker_waves_la(SM& sm, int wk, int lane, int nt
     add_staged(0);
   } else {
     for (int j0 = 0; j0 < nt;) {
-      const int j1 = group_end(j0, nt, Smem<T, NTM, false>::kStageTiles);
+      const int j1 = group_end(j0, nt, Smem<T, NTM, false, true>::kStageTiles);
       refresh_slots<SLOTS>(ti, tj);
       gen_group<T, NTHR>(sm, sm.panel, 64 * (wk + 1) + lane, j0, j1, nt, nA, d, two_nu, sigma2, tau2);
       __syncthreads();  // G1
@@ -786,9 +825,11 @@ __device__ __forceinline__ void worker_waves_la(SM& sm, int wk, int lane, int nt
     if (nt > 1) gen_column<T, NTHR - 64>(sm, stage, wtid, 1, 1, nt, nA, d, two_nu, sigma2, tau2);
   }
   __syncthreads();  // P0
+  SBV_PROF(8, wk == 0);
   for (int k = 0; k < nt; ++k) {
     refresh_slots<SLOTS>(ti, tj);
     if (kLateCov<T>) add_staged(k + 1);  // staged during the previous step (or up front)
+    T* const Pk = sm.panel + KP * (k & 1);  // column k of L
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
       if (tj[s] == k && ti[s] > k) {
@@ -796,17 +837,19 @@ __device__ __forceinline__ void worker_waves_la(SM& sm, int wk, int lane, int nt
 #pragma unroll
         for (int q = 0; q < 4; ++q) o = MF<T>::mma(acc[s][q], sm.negM[68 * q + oplane(lane)], o);
         acc[s] = o;
-        T* P = sm.panel + kOpT * ti[s];
+        T* P = Pk + kOpT * ti[s];
 #pragma unroll
         for (int t = 0; t < 4; ++t) P[opoff<T>(MF<T>::row(g, t), cl)] = o[t];
       }
     }
+    SBV_PROF(9, wk == 0);
     __syncthreads();  // S3
+    SBV_PROF(10, wk == 0);
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
       if (tj[s] > k) {
-        const T* Pj = sm.panel + kOpT * tj[s];
-        const T* Pi = sm.panel + kOpT * ti[s];
+        const T* Pj = Pk + kOpT * tj[s];
+        const T* Pi = Pk + kOpT * ti[s];
         acc_t o = acc[s];
 #pragma unroll
         for (int q = 0; q < 4; ++q) o = MF<T>::mma(Pj[68 * q + oplane(lane)], Pi[68 * q + oplane(lane)], o);
@@ -814,10 +857,13 @@ __device__ __forceinline__ void worker_waves_la(SM& sm, int wk, int lane, int nt
         if (ti[s] == k + 1 && tj[s] == k + 1) publish_diag(s, k + 1);
       }
     }
+    SBV_PROF(11, wk == 0);
     // covariance column k+2 while the panel wave factors diagonal tile k+1
     if (kLateCov<T> && k + 2 < nt)
       gen_column<T, NTHR - 64>(sm, stage, wtid, k + 2, k + 2, nt, nA, d, two_nu, sigma2, tau2);
+    SBV_PROF(12, wk == 0);
     __syncthreads();  // S4
+    SBV_PROF(13, wk == 0);
   }
 }
 
@@ -1111,7 +1157,7 @@ __global__ __launch_bounds__(NW * 64) void k_block_loglik(const SetDesc* __restr
                                                           const int* __restrict__ count,
                                                           double piv_tau, LargeArgs L) {
   static_assert(!PRE || (!SAMPLE && !LA && NTM == kLargeNTM), "large-block mode: no simulation, no lookahead");
-  __shared__ Smem<T, NTM, GRAD> sm;
+  __shared__ Smem<T, NTM, GRAD, LA> sm;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
