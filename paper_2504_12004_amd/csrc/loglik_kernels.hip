@@ -84,6 +84,23 @@ __device__ __forceinline__ double t_exp(double x) { return exp(x); }
 __device__ __forceinline__ float t_exp(float x) { return expf(x); }
 __device__ __forceinline__ double t_sqrt(double x) { return sqrt(x); }
 __device__ __forceinline__ float t_sqrt(float x) { return sqrtf(x); }
+// Distance from its square in the covariance generation (r2 >= 0): the
+// hardware reciprocal square root (about 23 good bits) refined by one coupled
+// Newton-Raphson step for sqrt(r2) and 1/(2 sqrt(r2)) and one residual
+// correction (Goldschmidt's square-root iteration as in Markstein's IA-64
+// elementary functions), which lands within rounding of the library sqrt.
+// Squared distances below 2^-1000 give 0: no covariance entry can tell them
+// apart.  FP32 takes the one-instruction hardware sqrt (1 ulp).
+__device__ __forceinline__ double g_sqrt(double r2) {
+  const double y = __builtin_amdgcn_rsq(r2);
+  double g = r2 * y, h = 0.5 * y;
+  const double e = fma(-h, g, 0.5);
+  g = fma(g, e, g);
+  h = fma(h, e, h);
+  g = fma(fma(-g, g, r2), h, g);
+  return r2 < 0x1p-1000 ? 0.0 : g;
+}
+__device__ __forceinline__ float g_sqrt(float r2) { return __builtin_amdgcn_sqrtf(r2); }
 
 // Scaled coordinates in LDS: one row of zld(d) elements per point (d rounded
 // up to 16 bytes, zero padded), so that the covariance generation reads them
@@ -426,7 +443,7 @@ __device__ __forceinline__ void gen_items(SM& sm, T* dst, const int (&e)[N], int
       if (pa[n][t] >= nA || pb[n] >= nA) {
         v = (pa[n][t] == pb[n]) ? T(-1) : T(0);
       } else {
-        v = -(sigma2 * matern<T>(t_sqrt(r2[n][t]), two_nu));
+        v = -(sigma2 * matern<T>(g_sqrt(r2[n][t]), two_nu));
         if (pa[n][t] == pb[n]) v -= tau2;
       }
       dst[256 * i[n] + 64 * t + l[n]] = v;
@@ -501,7 +518,7 @@ __device__ __forceinline__ void gen_group(SM& sm, T* dst, int tid, int j0, int j
       if (pa[t] >= nA || pb >= nA) {
         v[t] = (pa[t] == pb) ? T(-1) : T(0);
       } else {
-        v[t] = -(sigma2 * matern<T>(t_sqrt(r2[t]), two_nu));
+        v[t] = -(sigma2 * matern<T>(g_sqrt(r2[t]), two_nu));
         if (pa[t] == pb) v[t] -= tau2;
       }
     }
