@@ -188,6 +188,7 @@ struct Smem {
   T zfull[GRAD ? NTM * kTile : 1];  // all of z = L^{-1} y (GRAD only)
   T xi[NTM * kTile];                // innovations of the conditional simulator
   int la_flag;                      // lookahead: last diagonal step published
+  double isc[kMaxDim];              // exp(-theta_k) of the set being processed
 #ifdef SBV_PHASE_PROFILE
   unsigned long long prof[16];
 #endif
@@ -1185,11 +1186,17 @@ __global__ __launch_bounds__(NW * 64) void k_block_loglik(const SetDesc* __restr
   __syncthreads();
 #endif
 
+  int isc_set = -1;  // set whose coordinate scales sm.isc holds
   for (int it = blockIdx.x; it < total; it += gridDim.x) {
     const WorkItem w = itm[it];
     const SetDesc S = sets[w.set];
     const int d = S.d;
     const double* th = theta + S.theta_off;
+    if (w.set != isc_set) {  // uniform over the workgroup
+      if (tid < d) sm.isc[tid] = exp(-th[tid]);
+      __syncthreads();
+      isc_set = w.set;
+    }
     const int b0 = S.bptr[w.block], b1 = S.bptr[w.block + 1];
     const int64_t n0 = S.nptr[w.block], n1 = S.nptr[w.block + 1];
     const int mi = (int)(n1 - n0), bi = b1 - b0, nA = mi + bi;
@@ -1214,20 +1221,21 @@ __global__ __launch_bounds__(NW * 64) void k_block_loglik(const SetDesc* __restr
     const T* Wp = PRE ? reinterpret_cast<const T*>(L.W) + (int64_t)it * kLargeW : nullptr;
     const T* zp = PRE ? reinterpret_cast<const T*>(L.z) + (int64_t)it * kLargeZ : nullptr;
 
-    // gather A = J u B (J first): scaled coordinates and observations
+    // gather A = J u B (J first), one point per thread: scaled coordinates
+    // (rows of zld(d), zero padded) and observations
     const int ld = zld<T>(d);
-    for (int e = tid; e < nAl * ld; e += NW * 64) {
-      int pl = e / ld, k = e - pl * ld;
-      int pa = pl + off;
-      int pos = pa < mi ? S.nidx[n0 + pa] : b0 + (pa - mi);
-      sm.z[pl * ld + k] = k < d ? T(S.X[(int64_t)pos * d + k] * exp(-th[k])) : T(0);
-    }
     for (int pl = tid; pl < nt * kTile; pl += NW * 64) {
       const int pa = pl + off;
+      const bool real = pl < nAl;
+      const int pos = real ? (pa < mi ? S.nidx[n0 + pa] : b0 + (pa - mi)) : 0;
+      if (real) {
+        const double* xr = S.X + (int64_t)pos * d;
+        for (int k = 0; k < ld; ++k) sm.z[pl * ld + k] = k < d ? T(xr[k] * sm.isc[k]) : T(0);
+      }
       T v = T(0);
-      if (pl < nAl && (!SAMPLE || pa < mi)) v = T(S.y[pa < mi ? S.nidx[n0 + pa] : b0 + (pa - mi)]);
+      if (real && (!SAMPLE || pa < mi)) v = T(S.y[pos]);
       sm.yv[pl] = v;
-      if (SAMPLE) sm.xi[pl] = (pa >= mi && pl < nAl) ? T(S.xi[b0 + (pa - mi)]) : T(0);
+      if (SAMPLE) sm.xi[pl] = (pa >= mi && real) ? T(S.xi[b0 + (pa - mi)]) : T(0);
     }
     if (tid == 0) sm.la_flag = -1;
     __syncthreads();
