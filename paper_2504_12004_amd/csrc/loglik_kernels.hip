@@ -558,28 +558,39 @@ __device__ __forceinline__ int group_end(int j0, int nt, int cap) {
 // Forward-solve update of the observations in rows r0..r1-1 with the column
 // tile of L staged in the panel: y_rho -= L[rho][16k..16k+15] z_k, four rows
 // per lane as independent chains (y_update: rows r0..16nt-1 with z_k from LDS).
-template <typename T, class SM>
-__device__ __forceinline__ void y_update_rows(SM& sm, const T* P, int lane, int r0, int r1, const T (&zk)[16]) {
-  for (int base = r0; base < r1; base += 256) {
-    T v[4];
-    int rho[4];
+template <typename T, int IT, class SM>
+__device__ __forceinline__ void y_update_rows_t(SM& sm, const T* P, int lane, int r0, int r1, const T (&zk)[16]) {
+  for (int base = r0; base < r1; base += 64 * IT) {
+    T v[IT];
+    int rho[IT];
 #pragma unroll
-    for (int it = 0; it < 4; ++it) {
+    for (int it = 0; it < IT; ++it) {
       rho[it] = base + lane + 64 * it;
       v[it] = rho[it] < r1 ? sm.yv[rho[it]] : T(0);
     }
 #pragma unroll
     for (int c = 0; c < 16; ++c) {
 #pragma unroll
-      for (int it = 0; it < 4; ++it) {
+      for (int it = 0; it < IT; ++it) {
         const int rr = rho[it] < r1 ? rho[it] : r0;
         v[it] -= P[kOpT * (rr >> 4) + opoff<T>(rr & 15, c)] * zk[c];
       }
     }
 #pragma unroll
-    for (int it = 0; it < 4; ++it)
+    for (int it = 0; it < IT; ++it)
       if (rho[it] < r1) sm.yv[rho[it]] = v[it];
   }
+}
+// (as many rows per lane as the range needs, up to four)
+template <typename T, class SM>
+__device__ __forceinline__ void y_update_rows(SM& sm, const T* P, int lane, int r0, int r1, const T (&zk)[16]) {
+  const int rows = r1 - r0;
+  if (rows > 128)
+    y_update_rows_t<T, 4>(sm, P, lane, r0, r1, zk);
+  else if (rows > 64)
+    y_update_rows_t<T, 2>(sm, P, lane, r0, r1, zk);
+  else if (rows > 0)
+    y_update_rows_t<T, 1>(sm, P, lane, r0, r1, zk);
 }
 template <typename T, class SM>
 __device__ __forceinline__ void y_update(SM& sm, int lane, int r0, int nt) {
