@@ -862,9 +862,15 @@ __device__ __forceinline__ void worker_waves_la(SM& sm, int wk, int lane, int nt
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
       if (tj[s] == k && ti[s] > k) {
-        acc_t o = {T(0), T(0), T(0), T(0)};
+        // two independent MFMA chains (q even, q odd) halve the dependent latency
+        acc_t o = {T(0), T(0), T(0), T(0)}, o2 = {T(0), T(0), T(0), T(0)};
 #pragma unroll
-        for (int q = 0; q < 4; ++q) o = MF<T>::mma(acc[s][q], sm.negM[68 * q + oplane(lane)], o);
+        for (int q = 0; q < 4; q += 2) {
+          o = MF<T>::mma(acc[s][q], sm.negM[68 * q + oplane(lane)], o);
+          o2 = MF<T>::mma(acc[s][q + 1], sm.negM[68 * (q + 1) + oplane(lane)], o2);
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) o[t] += o2[t];
         acc[s] = o;
         T* P = Pk + kOpT * ti[s];
 #pragma unroll
@@ -1073,9 +1079,15 @@ __device__ __forceinline__ void worker_waves(SM& sm, int wk, int lane, int nt, i
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
       if (tj[s] == k && ti[s] > k) {
-        acc_t o = {T(0), T(0), T(0), T(0)};
+        // two independent MFMA chains (q even, q odd) halve the dependent latency
+        acc_t o = {T(0), T(0), T(0), T(0)}, o2 = {T(0), T(0), T(0), T(0)};
 #pragma unroll
-        for (int q = 0; q < 4; ++q) o = MF<T>::mma(acc[s][q], sm.negM[68 * q + oplane(lane)], o);
+        for (int q = 0; q < 4; q += 2) {
+          o = MF<T>::mma(acc[s][q], sm.negM[68 * q + oplane(lane)], o);
+          o2 = MF<T>::mma(acc[s][q + 1], sm.negM[68 * (q + 1) + oplane(lane)], o2);
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) o[t] += o2[t];
         acc[s] = o;
         T* P = sm.panel + kOpT * ti[s];
 #pragma unroll
