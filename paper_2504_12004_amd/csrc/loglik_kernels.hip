@@ -1079,15 +1079,21 @@ __device__ __forceinline__ void worker_waves(SM& sm, int wk, int lane, int nt, i
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
       if (tj[s] == k && ti[s] > k) {
-        // two independent MFMA chains (q even, q odd) halve the dependent latency
+        // two independent MFMA chains (q even, q odd) halve the dependent
+        // latency (one chain in the large-block variant: fewer live registers)
         acc_t o = {T(0), T(0), T(0), T(0)}, o2 = {T(0), T(0), T(0), T(0)};
+        if (PRE) {
 #pragma unroll
-        for (int q = 0; q < 4; q += 2) {
-          o = MF<T>::mma(acc[s][q], sm.negM[68 * q + oplane(lane)], o);
-          o2 = MF<T>::mma(acc[s][q + 1], sm.negM[68 * (q + 1) + oplane(lane)], o2);
+          for (int q = 0; q < 4; ++q) o = MF<T>::mma(acc[s][q], sm.negM[68 * q + oplane(lane)], o);
+        } else {
+#pragma unroll
+          for (int q = 0; q < 4; q += 2) {
+            o = MF<T>::mma(acc[s][q], sm.negM[68 * q + oplane(lane)], o);
+            o2 = MF<T>::mma(acc[s][q + 1], sm.negM[68 * (q + 1) + oplane(lane)], o2);
+          }
+#pragma unroll
+          for (int t = 0; t < 4; ++t) o[t] += o2[t];
         }
-#pragma unroll
-        for (int t = 0; t < 4; ++t) o[t] += o2[t];
         acc[s] = o;
         T* P = sm.panel + kOpT * ti[s];
 #pragma unroll
@@ -1247,11 +1253,21 @@ __global__ __launch_bounds__(NW * 64) void k_block_loglik(const SetDesc* __restr
     // gather A = J u B (J first), one point per thread: scaled coordinates
     // (rows of zld(d), zero padded) and observations
     const int ld = zld<T>(d);
+    if (PRE) {
+      // (the large-block variant keeps the element-wise gather, which costs it
+      // fewer register spills than the per-point one)
+      for (int e = tid; e < nAl * ld; e += NW * 64) {
+        const int pl = e / ld, k = e - pl * ld;
+        const int pa = pl + off;
+        const int pos = pa < mi ? S.nidx[n0 + pa] : b0 + (pa - mi);
+        sm.z[pl * ld + k] = k < d ? T(S.X[(int64_t)pos * d + k] * exp(-th[k])) : T(0);
+      }
+    }
     for (int pl = tid; pl < nt * kTile; pl += NW * 64) {
       const int pa = pl + off;
       const bool real = pl < nAl;
       const int pos = real ? (pa < mi ? S.nidx[n0 + pa] : b0 + (pa - mi)) : 0;
-      if (real) {
+      if (real && !PRE) {
         const double* xr = S.X + (int64_t)pos * d;
         for (int k = 0; k < ld; ++k) sm.z[pl * ld + k] = k < d ? T(xr[k] * sm.isc[k]) : T(0);
       }
