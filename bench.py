@@ -321,13 +321,23 @@ def cpu_baseline(B, X, sbv, theta, two_nu, seconds):
     O.sbv_loglik(X, y, O.subset(S, order[:64]), theta, two_nu, nthreads=threads)
     t_cal = max(time.perf_counter() - t0, 1e-4)
     nb = int(min(B.K, max(64, 64 * seconds / t_cal)))
-    sub = O.subset(S, order[:nb])
+    if nb < B.K:
+        sub = O.subset(S, order[:nb])
+        t0 = time.perf_counter()
+        O.sbv_loglik(X, y, sub, theta, two_nu, nthreads=threads)
+        t = time.perf_counter() - t0
+        full = t * B.K / nb
+        return {"value": 1.0 / full, "unit": "evals/s", "cores": threads, "kind": "oracle",
+                "sample": f"{nb} of {B.K} blocks (random), {t:.1f}s, scaled to the full dataset"}
+    # the whole dataset takes less than `seconds`: repeat full evaluations
+    reps = 0
     t0 = time.perf_counter()
-    O.sbv_loglik(X, y, sub, theta, two_nu, nthreads=threads)
+    while reps == 0 or time.perf_counter() - t0 < seconds:
+        O.sbv_loglik(X, y, S, theta, two_nu, nthreads=threads)
+        reps += 1
     t = time.perf_counter() - t0
-    full = t * B.K / nb
-    return {"value": 1.0 / full, "unit": "evals/s", "cores": threads, "kind": "oracle",
-            "sample": f"{nb} of {B.K} blocks (random), {t:.1f}s, scaled to the full dataset"}
+    return {"value": reps / t, "unit": "evals/s", "cores": threads, "kind": "oracle",
+            "sample": f"{reps} full evaluations ({B.K} blocks each), {t:.1f}s"}
 
 
 if __name__ == "__main__":
