@@ -62,7 +62,7 @@ def main():
         print(json.dumps({"copy_bytes": src.numel() * 8, "launches": 3}))
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+        print(json.dumps({"error": "the library and this benchmark run on one GPU; --gpus must be 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
 

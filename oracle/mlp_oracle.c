@@ -11,7 +11,7 @@
  *   L = 1/(N * out) sum (yhat - y)^2.
  * Adam (Kingma & Ba 2015) with bias correction.
  *
- * The features and the network are not in the paper; they are this build's own
+ * The features and the network are not in the paper; they are the library's own
  * warm-start component, so their parity is pinned only by finite differences
  * and closed-form checks (no paper values exist).
  */

@@ -227,7 +227,7 @@ def summarize(out, write_dir):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("what", choices=["run", "summarize", "all"])
-    ap.add_argument("--out", default=os.path.join(ROOT, "gpurun_out", "prof"))
+    ap.add_argument("--out", default=os.path.join(ROOT, "prof_raw"))
     ap.add_argument("--write", default=os.path.join(ROOT, "profiles"))
     a = ap.parse_args()
     rc = 0

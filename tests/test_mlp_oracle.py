@@ -1,6 +1,6 @@
 """Pins of the FP64 warm-start reference (network, Adam, summary statistics).
 
-The network and features are this build's own component (not in the paper),
+The network and features are the library's own component (not in the paper),
 so they are pinned by finite differences and closed forms only."""
 import numpy as np
 from scipy.special import erf
