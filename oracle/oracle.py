@@ -39,7 +39,7 @@ def lib():
         L.sbv_oracle_structure_get.argtypes = [C.c_void_p, _i64, _i64, _i64, _i64, _d]
         L.sbv_oracle_structure_free.argtypes = [C.c_void_p]
         L.sbv_oracle_sbv_loglik.argtypes = [_d, _d, C.c_int64, C.c_int, C.c_int64, _i64, _i64, _i64, _i64,
-                                            _d, C.c_int, _d, _d, _d, C.c_int]
+                                            _d, C.c_int, _d, _d, _d, C.c_int, _d]
         L.sbv_oracle_sample.argtypes = [_d, C.c_int64, C.c_int, C.c_int64, _i64, _i64, _i64, _i64, _d,
                                         C.c_int, _d, _d]
         if hasattr(L, "mlp_oracle_forward"):
@@ -151,17 +151,20 @@ def build(X, beta_build, K, m, lloyd_iters=10, min_bs=0, max_bs=0, seed=0):
     return Structure(n, d, m, bp, pts, npt, nidx[:nnz.value], obj[:nobj.value])
 
 
-def sbv_loglik(X, y, S, theta, two_nu, grad=False, blocks=False, nthreads=0):
+def sbv_loglik(X, y, S, theta, two_nu, grad=False, blocks=False, nthreads=0, parts=False):
     """SBV log-likelihood (sum of Alg. 5 block terms); optionally the per-block
-    terms and the gradient in log theta."""
+    terms, the gradient in log theta, and (parts=True, not with grad) each
+    block's u_i = v^T v and d_i = 2 log det L' as a K x 2 array."""
     X, y, th = _c64(X), _c64(y), _c64(theta)
     n, d = X.shape
     ll = np.zeros(1)
     lb = np.empty(S.K)
     g = np.zeros(d + 2)
+    ud = np.full((S.K, 2), np.nan) if parts else None
     st = lib().sbv_oracle_sbv_loglik(_p(X), _p(y), n, d, S.K, _p(S.block_ptr, _i64), _p(S.block_pts, _i64),
                                      _p(S.nn_ptr, _i64), _p(S.nn_idx if len(S.nn_idx) else np.zeros(1, np.int64), _i64),
-                                     _p(th), int(two_nu), _p(lb), _p(ll), _p(g) if grad else None, int(nthreads))
+                                     _p(th), int(two_nu), _p(lb), _p(ll), _p(g) if grad else None, int(nthreads),
+                                     _p(ud) if parts else None)
     if st == OR_EINVAL:
         raise ValueError("oracle sbv_loglik rejected its arguments")
     out = [ll[0]]
@@ -169,6 +172,8 @@ def sbv_loglik(X, y, S, theta, two_nu, grad=False, blocks=False, nthreads=0):
         out.append(g)
     if blocks:
         out.append(lb)
+    if parts:
+        out.append(ud)
     return out[0] if len(out) == 1 else tuple(out)
 
 

@@ -526,8 +526,10 @@ static void or_blk_fill(or_blk* B, const double* X, const double* y, int d,
 }
 
 /* Returns the block term l_i (Alg. 5 with readings R3, R4) or -inf if a
- * factorisation fails.  Work buffers are owned by the caller. */
-static double or_block_loglik(or_blk* B, double* work_v) {
+ * factorisation fails; when ud is given it receives the two data-dependent
+ * parts of Alg. 5 Step 2, u = v^T v and d = 2 log det L'.  Work buffers are
+ * owned by the caller. */
+static double or_block_loglik(or_blk* B, double* work_v, double* ud) {
   int64_t mi = B->mi, bi = B->bi;
   /* L <- POTRF(Sigma^con) */
   if (mi > 0 && or_chol(B->Scon, mi)) return -INFINITY;
@@ -551,6 +553,7 @@ static double or_block_loglik(or_blk* B, double* work_v) {
   /* u = v^T v; d = 2 log det L'; l_i = -1/2 (u + d + b_i log 2 pi)  (R4) */
   double u = 0.0, dd = 0.0;
   for (int64_t a = 0; a < bi; ++a) { u += work_v[a] * work_v[a]; dd += 2.0 * log(B->Slk[a * bi + a]); }
+  if (ud) { ud[0] = u; ud[1] = dd; }
   return -0.5 * (u + dd + (double)bi * OR_LOG2PI);
 }
 
@@ -684,7 +687,7 @@ int sbv_oracle_sbv_loglik(const double* X, const double* y, int64_t n, int d, in
                           const int64_t* block_ptr, const int64_t* block_pts,
                           const int64_t* nn_ptr, const int64_t* nn_idx,
                           const double* theta, int two_nu, double* ll_blocks, double* ll,
-                          double* grad, int nthreads) {
+                          double* grad, int nthreads, double* ud_blocks) {
   if (n <= 0 || d <= 0 || d > 64 || K <= 0) return OR_EINVAL;
   if (two_nu != 1 && two_nu != 3 && two_nu != 5 && two_nu != 7) return OR_EINVAL;
   if (or_check_structure(n, K, block_ptr, block_pts, nn_ptr, nn_idx)) return OR_EINVAL;
@@ -727,7 +730,7 @@ int sbv_oracle_sbv_loglik(const double* X, const double* y, int64_t n, int d, in
         wv = (double*)malloc(sizeof(double) * (cap_b + 1));
       }
       or_blk_fill(&B, X, y, d, J, mi, P, bi, beta, s2, t2, two_nu);
-      lb[r] = or_block_loglik(&B, wv);
+      lb[r] = or_block_loglik(&B, wv, ud_blocks ? ud_blocks + 2 * r : NULL);
       if (!isfinite(lb[r])) bad = 1;
     }
     free(B.Scon); free(B.Slk); free(B.Scross); free(B.yJ); free(B.yB); free(wv);

@@ -23,6 +23,8 @@ def to_gpu(sbv, X, y, S):
     return sbv.sbv_blocks_import(X, y, S.block_ptr, S.block_pts, S.nn_ptr, S.nn_idx)
 
 
-def block_tolerance(lb_ref, tol):
-    """Per-block diagnostic bound: tol * (|l_i| + size-scaled magnitude)."""
-    return tol * (np.abs(lb_ref) + 10.0)
+def block_tolerance(lb_ref, ud_ref, tol):
+    """Per-block bound tol * (|l_i| + |d_i| + u_i): l_i = -(u_i + d_i + b_i log 2 pi)/2
+    is a signed sum that can cancel to near 0, so its error is measured
+    against the size of its parts (u_i = v^T v, d_i = 2 log det L')."""
+    return tol * (np.abs(lb_ref) + np.abs(ud_ref[:, 1]) + ud_ref[:, 0])

@@ -22,14 +22,14 @@ def sbv():
 
 
 def _compare(sbv, X, y, th, S, two_nu, prec, tol):
-    ref, lb_ref = O.sbv_loglik(X, y, S, th, two_nu, blocks=True)
+    ref, lb_ref, ud_ref = O.sbv_loglik(X, y, S, th, two_nu, blocks=True, parts=True)
     B = to_gpu(sbv, X, y, S)
     got = sbv.sbv_loglik(B, th, two_nu, prec)[0]
     lb = sbv.sbv_blocks_terms(B)
-    worst = np.max(np.abs(lb - lb_ref) / (np.abs(lb_ref) + 10.0))
+    worst = np.max(np.abs(lb - lb_ref) / (np.abs(lb_ref) + np.abs(ud_ref[:, 1]) + ud_ref[:, 0]))
     print(f"ref {ref!r} got {got!r} rel {abs(got - ref) / abs(ref):.3e} worst block {worst:.3e}", flush=True)
     assert abs(got - ref) <= tol * abs(ref)
-    assert np.all(np.abs(lb - lb_ref) <= block_tolerance(lb_ref, tol * (10 if prec else 1)))
+    assert np.all(np.abs(lb - lb_ref) <= block_tolerance(lb_ref, ud_ref, tol))
     return B
 
 

@@ -66,3 +66,41 @@ def test_features_closed_form_for_a_linear_field():
         c0, c1, r2 = f[2 + 3 * r: 5 + 3 * r]
         assert abs(c0) < 1e-8 and abs(c1 - 9.0 / (2 * var)) < 1e-8 * c1 and abs(r2 - 1) < 1e-9
     assert len(f) == 4 + 5 * 3
+
+
+def test_adam_bias_correction_over_several_steps():
+    """Kingma & Ba, Algorithm 1, worked by hand.  With a constant gradient g
+    the corrected moments are exactly g and g^2, so every step is
+    lr * sign(g) (eps = 0).  With the gradient alternating g, -g, g the
+    corrected first moments are g, -(1 - b1)/(1 + b1) g and
+    (1 - b1 + b1^2)/(1 + b1 + b1^2) g while the corrected second moment stays
+    g^2.  A bias correction with a fixed exponent (1 - b1 for every t) fails
+    both from t = 2 on."""
+    b1, b2, lr = 0.9, 0.999, 0.01
+    g = np.array([0.3, -4.0, 2e-3])
+    p, m, v = np.array([1.0, -2.0, 0.5]), np.zeros(3), np.zeros(3)
+    for t in range(1, 6):
+        O.mlp_adam(p, g, m, v, t, lr, b1, b2, eps=0.0)
+        assert np.allclose(p, np.array([1.0, -2.0, 0.5]) - t * lr * np.sign(g), rtol=0, atol=1e-14)
+    p, m, v = np.zeros(3), np.zeros(3), np.zeros(3)
+    steps = [1.0, -(1 - b1) / (1 + b1), (1 - b1 + b1 ** 2) / (1 + b1 + b1 ** 2)]
+    expect = np.zeros(3)
+    for t, sgn in enumerate([1.0, -1.0, 1.0], start=1):
+        O.mlp_adam(p, sgn * g, m, v, t, lr, b1, b2, eps=0.0)
+        expect = expect - lr * steps[t - 1] * np.sign(g)
+        assert np.allclose(p, expect, rtol=0, atol=1e-14)
+
+
+def test_nearest_neighbour_semivariance_feature_closed_form():
+    """f1 = log of the mean over points of (y_i - y_nn(i))^2 / 2.  For a
+    linear field y = w x on an evenly spaced grid in d = 1 (spacing h, points
+    in shuffled order) every nearest neighbour is one grid step away, so
+    f1 = log(w^2 h^2 / 2) exactly (up to rounding)."""
+    n, h, w = 500, 1.0 / 500, 2.5
+    x = (np.random.default_rng(6).permutation(n) * h)[:, None]
+    y = w * x[:, 0]
+    f = O.features(x, y, np.arange(n))
+    assert abs(f[1] - np.log(0.5 * w * w * h * h)) < 1e-9
+    # the same field with a different slope moves f1 by log of the slope ratio squared
+    f2 = O.features(x, 3.0 * y, np.arange(n))
+    assert abs((f2[1] - f[1]) - np.log(9.0)) < 1e-9

@@ -297,3 +297,50 @@ def test_sampler_with_full_conditioning_is_cholesky_draw():
     P = S.block_pts
     L = np.linalg.cholesky(O.cov_matrix(X[P], X[P], th, 5, True))
     assert np.max(np.abs(y[P] - L @ xi[P])) < 1e-10
+
+
+# --- Alg. 1 Step 5: the total is a compensated sum ------------------------
+def test_total_is_compensated_where_plain_summation_fails():
+    """One block term near -1e16 followed by 2,000 terms of -log(2 pi)/2:
+    plain left-to-right FP64 summation drops every small term (each is below
+    half an ulp of 1e16), the compensated total must keep them.  The
+    reference is math.fsum (exactly rounded) of the oracle's own block terms;
+    the blocks are single points with no conditioning (m = 0), so each term
+    is -(y_i^2/s + log s + log 2 pi)/2 with s = sigma^2 + tau^2."""
+    import math
+    K = 2001
+    rng = np.random.default_rng(7)
+    X = rng.random((K, 1))
+    y = np.zeros(K)
+    y[0] = np.sqrt(2e16)  # s = 1: first term about -1e16
+    th = _theta([0.3], 1.0 - 1e-6, 1e-6)
+    ar = np.arange(K + 1)
+    S = O.Structure(K, 1, 0, ar, ar[:-1], np.zeros(K + 1, np.int64), np.zeros(0, np.int64))
+    tot, lb = O.sbv_loglik(X, y, S, th, 5, blocks=True)
+    exact = math.fsum(lb)
+    naive = 0.0
+    for v in lb:
+        naive += v
+    assert abs(naive - exact) > 1000.0  # plain summation is far off here
+    assert abs(tot - exact) <= 2.0 * np.spacing(abs(exact))
+    # the small terms are the closed form of a single-point block
+    assert np.allclose(lb[1:], -0.5 * np.log(2 * np.pi), rtol=0, atol=1e-15)
+
+
+def test_block_parts_recombine_to_the_term():
+    """u_i = v^T v and d_i = 2 log det L' that the oracle reports give back
+    l_i = -(u_i + d_i + b_i log 2 pi)/2 (Alg. 5 Step 2 with the constant of
+    Eq. (1)), and for a block without conditioning they are the quadratic form
+    and log-determinant of its own covariance (numpy Cholesky)."""
+    X, y, th = _data(300, 3, 41, [0.3, 0.5, 0.8], t2=1e-2)
+    S = O.build(X, np.exp(th[:3]), K=20, m=25, lloyd_iters=2, seed=3)
+    tot, lb, ud = O.sbv_loglik(X, y, S, th, 5, blocks=True, parts=True)
+    b = np.diff(S.block_ptr)
+    assert np.allclose(lb, -0.5 * (ud[:, 0] + ud[:, 1] + b * np.log(2 * np.pi)), rtol=1e-14, atol=1e-12)
+    B0, J0 = S.block(0)
+    assert len(J0) == 0
+    C0 = O.cov_matrix(X[B0], X[B0], th, 5, True)
+    L0 = np.linalg.cholesky(C0)
+    w = np.linalg.solve(L0, y[B0])
+    assert abs(ud[0, 0] - w @ w) < 1e-10 * max(1.0, w @ w)
+    assert abs(ud[0, 1] - 2 * np.sum(np.log(np.diag(L0)))) < 1e-10 * max(1.0, abs(ud[0, 1]))
