@@ -126,6 +126,26 @@ sbv_status sbv_loglik_dev(const sbv_blocks* sets, int32_t n_sets, const double* 
                           const int32_t* two_nu, int32_t prec, double* loglik_dev, void* stream);
 
 /*
+ * For callers that cannot allocate device memory (code queued inside a HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * log-likelihood of ONE handle, as sbv_loglik_dev computes it (same kernels,
+ * size buckets and reduction with the default kernel choice, so the same value
+ * bit for bit unless sbv_autotune changed that choice), queued on `stream` (a hipStream_t; NULL = default stream) with no
+ * allocation and no host synchronisation.  theta_dev (d+2 log-parameters) and
+ * loglik_dev (1 value, -inf when a block is not positive definite) are device
+ * pointers owned by the caller.  The per-block terms, flags, FP32 fallback
+ * lists and counters live in a fixed device array inside the library (about
+ * 5 MB per device, held until the process ends), so:
+ *  - the handle may have at most 262,144 blocks and joint sizes m_i + b_i up
+ *    to 272 (larger handles: SBV_E_INVAL, nothing queued);
+ *  - calls that overlap on one device (two host threads, or two streams
+ *    without ordering between them) share that array and race; order them;
+ *  - sbv_blocks_terms does not see the block terms of these calls.
+ */
+sbv_status sbv_loglik_noalloc_dev(sbv_blocks h, const double* theta_dev, int32_t two_nu, int32_t prec,
+                                  double* loglik_dev, void* stream);
+
+/*
  * Log-likelihood and its gradient with respect to the packed log-parameters
  * (structure and nu held fixed), from a hand-written adjoint of the block
  * factorisation.  grad: n_sets packed (d_j + 2) values, same order as theta.

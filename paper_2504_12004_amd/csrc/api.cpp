@@ -108,6 +108,12 @@ struct sbv_blocks_s {
   std::vector<SampleLevel> sample_levels;
   DevBuf<double> xi_ord, theta_s;
   DevBuf<SetDesc> sample_desc;
+  // work lists made with the handle (register variants only): bucket v's
+  // items are rl_items[rl_off[v] .. rl_off[v] + rl_count[v]), longest first
+  bool has_large = false;
+  std::vector<int> rl_variant, rl_off, rl_count;
+  DevBuf<WorkItem> rl_items;
+  DevBuf<int> rl_dcount;
 };
 
 // ---- evaluation plans ------------------------------------------------------
@@ -291,11 +297,7 @@ std::vector<TimedLaunch> g_timed;
 // this fraction of the original diagonal is recomputed in FP64.  The
 // environment variable SBV_PIV_TAU overrides it (read at every queued
 // evaluation; a captured graph keeps the value of its capture).
-double piv_tau() {
-  const char* e = std::getenv("SBV_PIV_TAU");
-  return e ? std::atof(e) : 1e-4;
-}
-#define g_piv_tau piv_tau()
+#define g_piv_tau sbv::fp32_pivot_tau()
 
 // Allocate the per-block adjoint buffers (e, g, Q: nA_i (b_i + 2) values per
 // block) of every set of a plan, once.
@@ -446,6 +448,31 @@ sbv_status sbv_internal_make_handle(const double* X, const double* y, int64_t n,
                                     const int64_t* nn_ptr, const int64_t* nn_idx, sbv_blocks* out);
 
 sbv_status sbv_internal_fail(sbv_status st, const char* msg) { return fail(st, msg); }
+
+double sbv::fp32_pivot_tau() {
+  const char* e = std::getenv("SBV_PIV_TAU");
+  return e ? std::atof(e) : 1e-4;
+}
+
+sbv_status sbv_internal_view(sbv_blocks h, HandleView* v) {
+  if (!h || !v) return fail(SBV_E_INVAL, "null handle");
+  v->X = h->X.p;
+  v->y = h->y.p;
+  v->bptr = h->bptr.p;
+  v->nptr = h->nptr.p;
+  v->nidx = h->nidx.p;
+  v->d = h->d;
+  v->K = h->K;
+  v->max_joint = h->max_joint;
+  v->has_large = h->has_large;
+  v->n_buckets = (int)h->rl_variant.size();
+  v->bucket_variant = h->rl_variant.data();
+  v->bucket_off = h->rl_off.data();
+  v->bucket_count = h->rl_count.data();
+  v->items = h->rl_items.p;
+  v->dcount = h->rl_dcount.p;
+  return SBV_OK;
+}
 
 extern "C" {
 
@@ -947,6 +974,35 @@ sbv_status sbv_internal_make_handle(const double* X, const double* y, int64_t n,
   HIP_TRY(hipMemcpy(h->nidx.p, ni.data(), sizeof(int32_t) * ni.size(), hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(h->pos_of.p, po.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice));
   HIP_TRY(hipMemset(h->flag.p, 0, sizeof(int32_t) * K));
+  // resident work lists: one bucket per register variant, longest first
+  {
+    const int nv = n_variants();
+    std::vector<std::vector<std::pair<int32_t, int32_t>>> per(nv);
+    for (int64_t r = 0; r < K; ++r) {
+      const int v = variant_for(h->joint[r]);
+      if (v < 0)
+        h->has_large = true;
+      else
+        per[v].push_back({h->joint[r], (int32_t)r});
+    }
+    std::vector<WorkItem> it;
+    std::vector<int> cnt;
+    for (int v = nv - 1; v >= 0; --v) {
+      if (per[v].empty()) continue;
+      std::stable_sort(per[v].begin(), per[v].end(), [](const auto& a, const auto& b) { return a.first > b.first; });
+      h->rl_variant.push_back(v);
+      h->rl_off.push_back((int)it.size());
+      h->rl_count.push_back((int)per[v].size());
+      for (const auto& e : per[v]) it.push_back(WorkItem{0, e.second});
+    }
+    if (!it.empty()) {
+      HIP_TRY(h->rl_items.alloc(it.size()));
+      HIP_TRY(hipMemcpy(h->rl_items.p, it.data(), sizeof(WorkItem) * it.size(), hipMemcpyHostToDevice));
+      HIP_TRY(h->rl_dcount.alloc(h->rl_count.size()));
+      HIP_TRY(hipMemcpy(h->rl_dcount.p, h->rl_count.data(), sizeof(int) * h->rl_count.size(),
+                        hipMemcpyHostToDevice));
+    }
+  }
   *out = h.release();
   return SBV_OK;
 }

@@ -115,6 +115,33 @@ hipError_t launch_large_grad(int prec, int grid, const SetDesc* sets, const doub
 }  // namespace sbv
 
 namespace sbv {
+
+// Read-only view of a handle for entry points outside the evaluation plans:
+// its device arrays and the work lists made when the handle was created (one
+// size bucket per register variant, longest joint size first, items of set 0,
+// all in one device array with one device count per bucket).
+struct HandleView {
+  const double* X;
+  const double* y;
+  const int32_t* bptr;
+  const int64_t* nptr;
+  const int32_t* nidx;
+  int32_t d;
+  int64_t K;
+  int32_t max_joint;
+  bool has_large;                 // some block needs the large-joint-set path
+  int n_buckets;
+  const int* bucket_variant;      // host, n_buckets
+  const int* bucket_off;          // host, n_buckets: offset into items
+  const int* bucket_count;        // host, n_buckets
+  const WorkItem* items;          // device, K items grouped by bucket
+  const int* dcount;              // device, n_buckets counts
+};
+
+// Pivot threshold of the FP32 path (a block whose FP32 pivot falls to or
+// below this fraction of its original diagonal is recomputed in FP64).
+double fp32_pivot_tau();
+
 hipError_t launch_gather_y(const double* y_ord, const int32_t* pos_of, double* y, int64_t n, hipStream_t s);
 hipError_t launch_scatter_y(const double* y, const int32_t* pos_of, double* y_ord, int64_t n,
                             hipStream_t s);

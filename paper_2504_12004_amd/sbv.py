@@ -74,6 +74,7 @@ def lib():
         "sbv_loglik": (C.c_int, [C.POINTER(_h), C.c_int32, _d, _i32, C.c_int32, _d]),
         "sbv_loglik_dev": (C.c_int, [C.POINTER(_h), C.c_int32, C.c_void_p, _i32, C.c_int32, C.c_void_p,
                                      C.c_void_p]),
+        "sbv_loglik_noalloc_dev": (C.c_int, [_h, C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p]),
         "sbv_loglik_grad": (C.c_int, [C.POINTER(_h), C.c_int32, _d, _i32, C.c_int32, _d, _d]),
         "sbv_loglik_grad_dev": (C.c_int, [C.POINTER(_h), C.c_int32, C.c_void_p, _i32, C.c_int32, C.c_void_p,
                                           C.c_void_p, C.c_void_p]),
@@ -228,6 +229,11 @@ def sbv_loglik_dev(sets, theta_dev, two_nu, out_dev, prec=SBV_FP64, stream=None)
     tn = np.ascontiguousarray(np.broadcast_to(np.asarray(two_nu, np.int32), (ns,)), dtype=np.int32)
     _check(lib().sbv_loglik_dev(hs, ns, C.c_void_p(_ptr(theta_dev)), _p(tn, _i32), int(prec),
                                 C.c_void_p(_ptr(out_dev)), C.c_void_p(_stream(stream))))
+
+
+def sbv_loglik_noalloc_dev(b, theta_dev, two_nu, out_dev, prec=SBV_FP64, stream=None):
+    _check(lib().sbv_loglik_noalloc_dev(b.handle, C.c_void_p(_ptr(theta_dev)), int(two_nu), int(prec),
+                                        C.c_void_p(_ptr(out_dev)), C.c_void_p(_stream(stream))))
 
 
 def sbv_loglik_grad(sets, theta, two_nu, prec=SBV_FP64):
