@@ -85,19 +85,16 @@ def main():
                              min_bs=w["min_bs"], max_bs=w["max_bs"], seed=w["seed"])
     t_build = time.perf_counter() - t0
     log(f"built structure: n={n} K={B.K} nnz={B.nnz} in {t_build:.2f}s")
-    # observations: Vecchia simulation on the device when available, else the
-    # standard-normal innovations themselves (timing does not depend on y)
-    y_source = "vecchia-sampler"
-    try:
-        theta_gen = torch.tensor(theta_true, dtype=torch.float64, device=dev)
-        xi_d = torch.tensor(xi, dtype=torch.float64, device=dev)
-        y_d = torch.empty(n, dtype=torch.float64, device=dev)
-        sbv.sbv_sample_dev(B, theta_gen, two_nu, xi_d, y_d)
-        sbv.sbv_blocks_set_y_dev(B, y_d)
-    except (AttributeError, sbv.SBVError):
-        y_source = "iid-normal"
-        sbv.sbv_blocks_set_y(B, xi)
+    # observations: the device Vecchia simulator at the true parameters on an
+    # independent generating structure (own seed, m_gen >= m)
+    t0 = time.perf_counter()
+    y_d = simulate(sbv, torch, dev, X, theta_true, xi, two_nu, w)
+    sbv.sbv_blocks_set_y_dev(B, y_d)
     torch.cuda.synchronize()
+    y_host = y_d.cpu().numpy()
+    y_source = (f"vecchia-sampler, generating structure m_gen={w['m_gen']} "
+                f"K_gen={n // w['gen_bs_mean']} blocks<={w['gen_max_bs']}")
+    log(f"simulated observations in {time.perf_counter() - t0:.2f}s")
 
     # per size bucket, pick the fastest kernel variant and schedule (setup, not timed)
     tuned, sched = {}, {}
@@ -150,21 +147,22 @@ def main():
     log(f"dominant kernel: variant with {tiles[v_dom]} tiles, {avg_ms:.3f} ms/launch, "
         f"{achieved / 1e12:.2f} TFLOP/s algorithmic")
 
-    grad_rate = None
-    try:
-        g_d = torch.empty(d + 2, dtype=torch.float64, device=dev)
+    grad_rate = {}
+    g_d = torch.empty(d + 2, dtype=torch.float64, device=dev)
+    for name, prec in (("fp64", sbv.SBV_FP64), ("fp32", sbv.SBV_FP32)):
         for i in range(2):
-            sbv.sbv_loglik_grad_dev(B, th_d[i], two_nu, out[i:i + 1], g_d, sbv.SBV_FP64, stream)
+            sbv.sbv_loglik_grad_dev(B, th_d[i], two_nu, out[i:i + 1], g_d, prec, stream)
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
         for i in range(kin):
-            sbv.sbv_loglik_grad_dev(B, th_d[i % len(thetas)], two_nu, out[i:i + 1], g_d, sbv.SBV_FP64, stream)
+            sbv.sbv_loglik_grad_dev(B, th_d[i % len(thetas)], two_nu, out[i:i + 1], g_d, prec, stream)
         e1.record(stream)
         torch.cuda.synchronize()
-        grad_rate = 1000.0 * kin / e0.elapsed_time(e1)
-    except sbv.SBVError:
-        pass
+        grad_rate[name] = 1000.0 * kin / e0.elapsed_time(e1)
+    log(f"loglik + gradient: {grad_rate['fp64']:.2f} evals/s FP64, {grad_rate['fp32']:.2f} evals/s FP32")
+
+    small = small_leg(sbv, torch, dev, stream)
 
     fits = None
     if args.fit_evals > 0:
@@ -172,7 +170,7 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(B, X, sbv, theta_true, two_nu, args.cpu_seconds)
+        cpu = cpu_baseline(B, X, y_host, sbv, torch, dev, thetas[0], two_nu, args.cpu_seconds, small)
 
     large = None
     if args.large_steps > 0:
@@ -202,7 +200,9 @@ def main():
             "fp32_evals_per_s": 1000.0 * kin / ms32,
             "fp32_max_rel_diff_vs_fp64": rel32,
             "fp32_fallback_blocks": int(fb),
-            "grad_fp64_evals_per_s": grad_rate,
+            "grad_fp64_evals_per_s": grad_rate["fp64"],
+            "grad_fp32_evals_per_s": grad_rate["fp32"],
+            "small_20k": {k: v for k, v in small.items() if not k.startswith("_")},
             "build_seconds": t_build,
             "autotuned_tiles": tuned,
             "autotuned_schedules": sched,
@@ -213,6 +213,61 @@ def main():
     if cpu is not None:
         res["cpu_baseline"] = cpu
     print(json.dumps(res), flush=True)
+
+
+def simulate(sbv, torch, dev, X, theta, xi, two_nu, w):
+    """Observations at the true parameters: the device conditional simulator on
+    a generating structure built independently of the evaluation structure
+    (its own seed, m_gen conditioning points, blocks of at most gen_max_bs
+    points so that every joint set fits the simulator).  Returns y (device,
+    original point order)."""
+    n, d = X.shape
+    G = sbv.sbv_build_blocks(X, None, np.exp(theta[:d]), max(1, n // w["gen_bs_mean"]), w["m_gen"],
+                             method=sbv.SBV_KMEANS, lloyd_iters=1, min_bs=0, max_bs=w["gen_max_bs"],
+                             seed=w["seed"] + 7919)
+    th = torch.tensor(theta, dtype=torch.float64, device=dev)
+    xi_d = torch.tensor(xi, dtype=torch.float64, device=dev)
+    y = torch.empty(n, dtype=torch.float64, device=dev)
+    sbv.sbv_sample_dev(G, th, two_nu, xi_d, y)
+    torch.cuda.synchronize()
+    G.free()
+    return y
+
+
+def small_leg(sbv, torch, dev, stream, steps=100):
+    """The n = 20,000, d = 10, Matern-5/2, tau^2 = 1e-6, 1,000-block, m = 60
+    workload at its true theta: FP64 evaluations per second (structure built
+    on the GPU, observations from the simulator)."""
+    from paper_2504_12004_amd import synth
+    w = synth.dataset("small_fp64")
+    X, theta, xi = w["X"], w["theta"], w["xi"]
+    d = X.shape[1]
+    B = sbv.sbv_build_blocks(X, None, np.exp(theta[:d]), w["K"], w["m"], method=sbv.SBV_KMEANS,
+                             lloyd_iters=w["lloyd_iters"], seed=w["seed"])
+    y = simulate(sbv, torch, dev, X, theta, xi, w["two_nu"], w)
+    sbv.sbv_blocks_set_y_dev(B, y)
+    th = torch.tensor(theta, dtype=torch.float64, device=dev)
+    out = torch.empty(steps + 3, dtype=torch.float64, device=dev)
+    for i in range(3):
+        sbv.sbv_loglik_dev(B, th, w["two_nu"], out[i:i + 1], sbv.SBV_FP64, stream)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for i in range(steps):
+        sbv.sbv_loglik_dev(B, th, w["two_nu"], out[3 + i:4 + i], sbv.SBV_FP64, stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    flops, _ = sbv.sbv_plan_flops(B, w["two_nu"])
+    res = {"workload": "small_20k: n=2e4 d=10 Matern-5/2 tau2=1e-6 kmeans K=1000 m=60, true theta",
+           "evals_per_s": 1000.0 / ms, "ms_per_eval": ms, "loglik_fp64": float(out[3].item()),
+           "total_algorithmic_tflops": float(np.sum(flops)) / (ms * 1e-3) / 1e12}
+    log(f"small_20k: {ms:.3f} ms/eval")
+    # kept for the oracle comparison of the CPU-baseline leg
+    res["_X"], res["_y"], res["_theta"], res["_two_nu"] = X, y.cpu().numpy(), theta, w["two_nu"]
+    res["_structure"] = sbv.sbv_blocks_export(B)
+    B.free()
+    return res
 
 
 def large_leg(sbv, torch, dev, stream, steps):
@@ -306,38 +361,52 @@ def traffic(path):
     return t.get("bytes_per_launch")
 
 
-def cpu_baseline(B, X, sbv, theta, two_nu, seconds):
-    """The FP64 oracle on a bounded sample of the same workload's blocks,
-    scaled to evaluations per second of the whole dataset."""
+def cpu_baseline(B, X, y, sbv, torch, dev, theta, two_nu, seconds, small):
+    """The FP64 oracle on a bounded sample of the same workload's blocks (real
+    observations, the first evaluation point), scaled to evaluations per
+    second of the whole dataset.  The same oracle evaluations check the
+    device values at the full size: the GPU's per-block terms of those blocks
+    (FP64 and FP32) against the oracle's, and the whole n = 2e4 workload."""
     import oracle as O
     bp, pts, npt, nid = sbv.sbv_blocks_export(B)
     S = O.Structure(B.n, B.d, 0, bp, pts, npt, nid)
-    y = np.zeros(B.n)
     rng = np.random.default_rng(0)
     order = rng.permutation(B.K)
     threads = len(os.sched_getaffinity(0))
+    # device block terms at theta (FP64, then FP32 with its fallback pass)
+    th_d = torch.tensor(theta, dtype=torch.float64, device=dev)
+    o = torch.empty(2, dtype=torch.float64, device=dev)
+    terms = {}
+    for name, prec in (("fp64", sbv.SBV_FP64), ("fp32", sbv.SBV_FP32)):
+        sbv.sbv_loglik_dev(B, th_d, two_nu, o[:1], prec)
+        torch.cuda.synchronize()
+        terms[name] = sbv.sbv_blocks_terms(B)
     # calibrate on 64 blocks, then take enough blocks for about `seconds`
     t0 = time.perf_counter()
     O.sbv_loglik(X, y, O.subset(S, order[:64]), theta, two_nu, nthreads=threads)
     t_cal = max(time.perf_counter() - t0, 1e-4)
     nb = int(min(B.K, max(64, 64 * seconds / t_cal)))
-    if nb < B.K:
-        sub = O.subset(S, order[:nb])
-        t0 = time.perf_counter()
-        O.sbv_loglik(X, y, sub, theta, two_nu, nthreads=threads)
-        t = time.perf_counter() - t0
-        full = t * B.K / nb
-        return {"value": 1.0 / full, "unit": "evals/s", "cores": threads, "kind": "oracle",
-                "sample": f"{nb} of {B.K} blocks (random), {t:.1f}s, scaled to the full dataset"}
-    # the whole dataset takes less than `seconds`: repeat full evaluations
-    reps = 0
+    blocks = np.sort(order[:nb])
+    sub = O.subset(S, blocks)
     t0 = time.perf_counter()
-    while reps == 0 or time.perf_counter() - t0 < seconds:
-        O.sbv_loglik(X, y, S, theta, two_nu, nthreads=threads)
-        reps += 1
+    tot, lb, ud = O.sbv_loglik(X, y, sub, theta, two_nu, blocks=True, parts=True, nthreads=threads)
     t = time.perf_counter() - t0
-    return {"value": reps / t, "unit": "evals/s", "cores": threads, "kind": "oracle",
-            "sample": f"{reps} full evaluations ({B.K} blocks each), {t:.1f}s"}
+    scale = np.abs(lb) + np.abs(ud[:, 1]) + ud[:, 0]
+    parity = {"blocks_checked": int(nb), "of_blocks": int(B.K), "theta": "first evaluation point"}
+    for name in ("fp64", "fp32"):
+        g = terms[name][blocks]
+        parity[f"{name}_max_block_rel"] = float(np.max(np.abs(g - lb) / scale))
+        parity[f"{name}_subset_sum_rel"] = float(abs(np.sum(g) - tot) / abs(tot))
+    # the n = 2e4 workload, whole dataset
+    if small is not None:
+        Ss = O.Structure(len(small["_X"]), small["_X"].shape[1], 0, *small["_structure"])
+        ref = O.sbv_loglik(small["_X"], small["_y"], Ss, small["_theta"], small["_two_nu"], nthreads=threads)
+        parity["small_20k_fp64_rel"] = float(abs(small["loglik_fp64"] - ref) / abs(ref))
+    log(f"parity vs oracle: {parity}")
+    full = t * B.K / nb
+    return {"value": 1.0 / full, "unit": "evals/s", "cores": threads, "kind": "oracle",
+            "sample": f"{nb} of {B.K} blocks (random), {t:.1f}s, scaled to the full dataset",
+            "parity": parity}
 
 
 if __name__ == "__main__":

@@ -149,6 +149,9 @@ sbv_status sbv_loglik_noalloc_dev(sbv_blocks h, const double* theta_dev, int32_t
  * Log-likelihood and its gradient with respect to the packed log-parameters
  * (structure and nu held fixed), from a hand-written adjoint of the block
  * factorisation.  grad: n_sets packed (d_j + 2) values, same order as theta.
+ * A set with a block that is not positive definite in FP64 gets l = -inf and
+ * a NaN gradient (host variant: SBV_E_NOTPD naming the set; other sets stay
+ * valid).
  */
 sbv_status sbv_loglik_grad(const sbv_blocks* sets, int32_t n_sets, const double* theta,
                            const int32_t* two_nu, int32_t prec, double* loglik, double* grad);
@@ -181,7 +184,8 @@ typedef struct {
   double ftol;                /* Nelder-Mead: stop when the simplex spread of -l is <= ftol |l|;   */
                               /* L-BFGS: stop when one iteration changes -l by <= ftol |l|         */
   double gtol;                /* L-BFGS: stop when max |dl/dtheta_k| <= gtol                        */
-  int32_t rebuild_rounds;     /* must be 0 (the structure is fixed during a fit)                   */
+  int32_t rebuild_rounds;     /* outer rounds that rebuild the structure at the fitted ranges and   */
+                              /* refit (0: the structure stays fixed); needs a built handle         */
   int32_t lbfgs_m;            /* L-BFGS memory (0: 10)                                              */
   double init_step;           /* Nelder-Mead initial simplex edge in log-parameter units (0: 0.5)  */
   const char* checkpoint_path;/* optional JSON state file, rewritten every iteration; if it exists */
@@ -203,11 +207,19 @@ sbv_status sbv_minimize(int32_t method, int32_t n, double* x, sbv_objective fn, 
 
 /*
  * Maximum-likelihood estimate of theta (the d+2 log-parameters) on one handle,
- * maximising the SBV log-likelihood with the device evaluations (the paper's
- * MLE loop).  theta_hat receives the optimum, loglik_fp64 a final FP64
- * evaluation there (always FP64, whatever o->prec), n_evals the objective
- * evaluations used, seconds the wall time.  SBV_E_NOCONV: max_evals reached
- * (outputs still written).
+ * maximising the SBV log-likelihood with the device evaluations: the
+ * optimiser loop of Alg. 1 (Steps 4-5 repeated until convergence; Sec. 8 runs
+ * it with NLopt).  theta0: host, d+2 finite values (else SBV_E_INVAL).
+ * theta_hat receives the optimum, loglik_fp64 a final FP64 evaluation there
+ * (always FP64, whatever o->prec), n_evals the objective evaluations used
+ * (all rounds), seconds the wall time.  The structure is built at fixed
+ * ranges (Sec. 4.4 scales the inputs before clustering); with
+ * o->rebuild_rounds = R > 0 the fit is followed by R rounds that rebuild the
+ * handle's structure with its own recipe (sbv_build_blocks arguments) at the
+ * fitted ranges exp(theta_hat[0:d]) and continue the fit from there, so the
+ * handle then holds the last rebuilt structure (handles from
+ * sbv_blocks_import: SBV_E_INVAL).  SBV_E_NOCONV: max_evals reached (outputs
+ * still written).
  */
 sbv_status sbv_fit(sbv_blocks set, const double* theta0, int32_t two_nu, const sbv_fit_opts* o,
                    double* theta_hat, double* loglik_fp64, int32_t* n_evals, double* seconds);

@@ -108,6 +108,12 @@ struct sbv_blocks_s {
   std::vector<SampleLevel> sample_levels;
   DevBuf<double> xi_ord, theta_s;
   DevBuf<SetDesc> sample_desc;
+  // build recipe of a handle made by sbv_build_blocks (for rebuilds at new ranges)
+  bool built = false;
+  std::vector<double> beta_build;
+  int64_t k_req = 0;
+  int32_t m_req = 0;
+  sbv_build_opts bopts{};
   // work lists made with the handle (register variants only): bucket v's
   // items are rl_items[rl_off[v] .. rl_off[v] + rl_count[v]), longest first
   bool has_large = false;
@@ -360,7 +366,7 @@ sbv_status run_plan_grad(Plan* P, int32_t prec, hipStream_t s) {
     }
   }
   HIP_TRY(launch_reduce(P->dsets.p, (int)P->sets.size(), nullptr, P->out.p, P->bad.p, s));
-  HIP_TRY(launch_reduce_grad(P->dsets.p, (int)P->sets.size(), P->grad.p, s));
+  HIP_TRY(launch_reduce_grad(P->dsets.p, (int)P->sets.size(), P->grad.p, P->bad.p, s));
   return SBV_OK;
 }
 
@@ -448,6 +454,42 @@ sbv_status sbv_internal_make_handle(const double* X, const double* y, int64_t n,
                                     const int64_t* nn_ptr, const int64_t* nn_idx, sbv_blocks* out);
 
 sbv_status sbv_internal_fail(sbv_status st, const char* msg) { return fail(st, msg); }
+
+void sbv_internal_set_build(sbv_blocks h, const double* beta_build, int64_t K, int32_t m, const sbv_build_opts& o) {
+  h->built = true;
+  h->beta_build.assign(beta_build, beta_build + h->d);
+  h->k_req = K;
+  h->m_req = m;
+  h->bopts = o;
+}
+
+bool sbv_internal_was_built(sbv_blocks h) { return h && h->built; }
+
+// Replace h's structure by a fresh build of its own points and observations
+// with the same recipe at new ranges beta_build (d values).  Plans that refer
+// to h are dropped; the handle pointer stays valid.
+sbv_status sbv_internal_rebuild(sbv_blocks h, const double* beta_build) {
+  if (!h || !h->built) return fail(SBV_E_INVAL, "the handle was not made by sbv_build_blocks");
+  const int64_t n = h->n;
+  const int d = h->d;
+  std::vector<double> Xo((size_t)n * d), yo(n), X((size_t)n * d), y(n);
+  HIP_TRY(hipDeviceSynchronize());
+  HIP_TRY(hipMemcpy(Xo.data(), h->X.p, sizeof(double) * n * d, hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(yo.data(), h->y.p, sizeof(double) * n, hipMemcpyDeviceToHost));
+  for (int64_t t = 0; t < n; ++t) {
+    const int64_t p = h->block_pts[t];
+    std::memcpy(&X[(size_t)p * d], &Xo[(size_t)t * d], sizeof(double) * d);
+    y[p] = yo[t];
+  }
+  sbv_blocks nh = nullptr;
+  sbv_status st = sbv_build_blocks(X.data(), y.data(), n, d, beta_build, h->k_req, h->m_req, &h->bopts, &nh);
+  if (st) return st;
+  drop_plans_of(h);
+  drop_plans_of(nh);
+  std::swap(*h, *nh);
+  sbv_blocks_free(nh);  // now holds the old structure
+  return SBV_OK;
+}
 
 double sbv::fp32_pivot_tau() {
   const char* e = std::getenv("SBV_PIV_TAU");

@@ -35,6 +35,7 @@ int knn_max_m();
 }  // namespace sbv
 
 sbv_status sbv_internal_fail(sbv_status st, const char* msg);
+void sbv_internal_set_build(sbv_blocks h, const double* beta_build, int64_t K, int32_t m, const sbv_build_opts& o);
 sbv_status sbv_internal_make_handle(const double* X, const double* y, int64_t n, int32_t d, int64_t K,
                                     const int64_t* block_ptr, const int64_t* block_pts,
                                     const int64_t* nn_ptr, const int64_t* nn_idx, sbv_blocks* out);
@@ -316,5 +317,7 @@ extern "C" sbv_status sbv_build_blocks(const double* X, const double* y, int64_t
   std::vector<int64_t> nidx(std::max<int64_t>(nnz, 1));
   for (int64_t t = 0; t < nnz; ++t) nidx[t] = pts[npos[t]];
   // 9. pack
-  return sbv_internal_make_handle(X, y, n, d, K, bptr.data(), pts.data(), nptr.data(), nidx.data(), out);
+  st = sbv_internal_make_handle(X, y, n, d, K, bptr.data(), pts.data(), nptr.data(), nidx.data(), out);
+  if (st == SBV_OK) sbv_internal_set_build(*out, beta_build, n_blocks, m, o);
+  return st;
 }

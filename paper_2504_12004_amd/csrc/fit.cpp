@@ -25,6 +25,8 @@
 #include "../../include/sbv.h"
 
 sbv_status sbv_internal_fail(sbv_status st, const char* msg);
+bool sbv_internal_was_built(sbv_blocks h);
+sbv_status sbv_internal_rebuild(sbv_blocks h, const double* beta_build);
 
 namespace {
 
@@ -490,39 +492,64 @@ sbv_status sbv_minimize(int32_t method, int32_t n, double* x, sbv_objective fn, 
 sbv_status sbv_fit(sbv_blocks set, const double* theta0, int32_t two_nu, const sbv_fit_opts* o, double* theta_hat,
                    double* loglik_fp64, int32_t* n_evals, double* seconds) {
   if (!set || !theta0 || !o || !theta_hat) return sbv_internal_fail(SBV_E_INVAL, "set, theta0, o, theta_hat required");
-  if (o->rebuild_rounds != 0) return sbv_internal_fail(SBV_E_INVAL, "rebuild_rounds is not supported (use 0)");
+  if (o->rebuild_rounds < 0) return sbv_internal_fail(SBV_E_INVAL, "rebuild_rounds must be >= 0");
+  if (o->rebuild_rounds > 0 && !sbv_internal_was_built(set))
+    return sbv_internal_fail(SBV_E_INVAL, "rebuild_rounds > 0 needs a handle made by sbv_build_blocks");
   if (o->prec != SBV_FP64 && o->prec != SBV_FP32) return sbv_internal_fail(SBV_E_INVAL, "bad precision");
   int64_t n;
   int32_t d;
   sbv_blocks_info(set, &n, &d, nullptr, nullptr);
+  for (int k = 0; k < d + 2; ++k)
+    if (!std::isfinite(theta0[k])) return sbv_internal_fail(SBV_E_INVAL, "theta0 has non-finite values");
   const auto t0 = std::chrono::steady_clock::now();
   std::vector<double> x(theta0, theta0 + d + 2);
-  FitCtx c{set, two_nu, o->prec};
-  Objective obj{fit_objective, &c};
-  double fb = INFINITY;
+  int64_t evals = 0;
   bool conv = false;
-  // With an FP64 polish to follow, the FP32 phase stops once an iteration
-  // changes -l by less than kFp32Ftol relative: below that, FP32 rounding of
-  // the block terms hides real progress and line searches only fail.
-  constexpr double kFp32Ftol = 1e-7;
-  sbv_fit_opts first = *o;
-  const bool coarse = o->fp64_polish && o->prec == SBV_FP32;
-  if (coarse) first.ftol = std::max(o->ftol, kFp32Ftol);
-  sbv_status st = run_minimize(o->optimizer, x, obj, first, fb, conv, coarse);
-  if (st) return st;
-  if (c.last != SBV_OK) return c.last;
-  int64_t evals = obj.evals;
-  if (o->fp64_polish && o->prec == SBV_FP32) {
-    // finish in FP64 from the FP32 optimum (no checkpoint for the polish)
-    sbv_fit_opts po = *o;
-    po.prec = SBV_FP64;
-    po.checkpoint_path = nullptr;
-    po.max_evals = std::max<int32_t>(o->max_evals - (int32_t)evals, 1);
-    FitCtx c2{set, two_nu, SBV_FP64};
-    Objective obj2{fit_objective, &c2};
-    st = run_minimize(o->optimizer, x, obj2, po, fb, conv);
+  // One optimisation on the handle's current structure, from x.
+  auto one_fit = [&](const sbv_fit_opts& oo) -> sbv_status {
+    FitCtx c{set, two_nu, oo.prec};
+    Objective obj{fit_objective, &c};
+    double fb = INFINITY;
+    // With an FP64 polish to follow, the FP32 phase stops once an iteration
+    // changes -l by less than kFp32Ftol relative: below that, FP32 rounding of
+    // the block terms hides real progress and line searches only fail.
+    constexpr double kFp32Ftol = 1e-7;
+    sbv_fit_opts first = oo;
+    const bool coarse = oo.fp64_polish && oo.prec == SBV_FP32;
+    if (coarse) first.ftol = std::max(oo.ftol, kFp32Ftol);
+    first.max_evals = std::max<int32_t>(oo.max_evals - (int32_t)evals, 1);
+    sbv_status st = run_minimize(oo.optimizer, x, obj, first, fb, conv, coarse);
     if (st) return st;
-    evals += obj2.evals;
+    if (c.last != SBV_OK) return c.last;
+    evals += obj.evals;
+    if (coarse) {
+      // finish in FP64 from the FP32 optimum (no checkpoint for the polish)
+      sbv_fit_opts po = oo;
+      po.prec = SBV_FP64;
+      po.checkpoint_path = nullptr;
+      po.max_evals = std::max<int32_t>(oo.max_evals - (int32_t)evals, 1);
+      FitCtx c2{set, two_nu, SBV_FP64};
+      Objective obj2{fit_objective, &c2};
+      st = run_minimize(oo.optimizer, x, obj2, po, fb, conv);
+      if (st) return st;
+      evals += obj2.evals;
+    }
+    return SBV_OK;
+  };
+  sbv_status st = one_fit(*o);
+  if (st) return st;
+  // Outer rounds: rebuild the structure (blocks, order, neighbours) at the
+  // fitted ranges, then continue the fit from the current optimum.  Checkpoints
+  // belong to the first round only.
+  for (int r = 0; r < o->rebuild_rounds; ++r) {
+    std::vector<double> beta(d);
+    for (int k = 0; k < d; ++k) beta[k] = std::exp(x[k]);
+    st = sbv_internal_rebuild(set, beta.data());
+    if (st) return st;
+    sbv_fit_opts later = *o;
+    later.checkpoint_path = nullptr;
+    st = one_fit(later);
+    if (st) return st;
   }
   double l64 = -INFINITY;
   st = sbv_loglik(&set, 1, x.data(), &two_nu, SBV_FP64, &l64);

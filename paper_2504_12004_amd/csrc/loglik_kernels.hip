@@ -2110,9 +2110,10 @@ hipError_t launch_reduce(const SetDesc* sets, int n_sets, const int* set_k, doub
 }
 
 // Per-set gradient: sum of the per-block terms in a fixed order, one
-// workgroup per set, one pass per parameter.
+// workgroup per set, one pass per parameter.  A set whose log-likelihood
+// reduction found a block that is not positive definite (bad != 0) gets NaN.
 __global__ __launch_bounds__(256) void k_reduce_grad(const SetDesc* __restrict__ sets,
-                                                     double* __restrict__ out) {
+                                                     double* __restrict__ out, const int* __restrict__ bad) {
   __shared__ double red[256];
   const SetDesc S = sets[blockIdx.x];
   const int np = S.d + 2;
@@ -2125,13 +2126,13 @@ __global__ __launch_bounds__(256) void k_reduce_grad(const SetDesc* __restrict__
       if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
       __syncthreads();
     }
-    if (threadIdx.x == 0) out[S.theta_off + k] = red[0];
+    if (threadIdx.x == 0) out[S.theta_off + k] = (bad && bad[blockIdx.x]) ? __builtin_nan("") : red[0];
     __syncthreads();
   }
 }
 
-hipError_t launch_reduce_grad(const SetDesc* sets, int n_sets, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_reduce_grad, dim3(n_sets), dim3(256), 0, s, sets, out);
+hipError_t launch_reduce_grad(const SetDesc* sets, int n_sets, double* out, const int* bad, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce_grad, dim3(n_sets), dim3(256), 0, s, sets, out, bad);
   return hipGetLastError();
 }
 

@@ -93,7 +93,9 @@ hipError_t launch_contract(int prec, int variant, int grid, const SetDesc* sets,
                            const WorkItem* items, const int* count, hipStream_t s);
 hipError_t launch_sample(int variant, int grid, const SetDesc* sets, const double* theta,
                          const WorkItem* items, const int* count, hipStream_t s);
-hipError_t launch_reduce_grad(const SetDesc* sets, int n_sets, double* out, hipStream_t s);
+// bad (n_sets, may be null): the not-positive-definite flags written by
+// launch_reduce; a flagged set's gradient is NaN.
+hipError_t launch_reduce_grad(const SetDesc* sets, int n_sets, double* out, const int* bad, hipStream_t s);
 int n_variants();
 Variant variant(int v);
 int variant_for(int nA);  // smallest variant holding a joint size nA, or -1

@@ -129,13 +129,22 @@ def _p(a, t=_d):
 
 
 class Blocks:
-    """Owning wrapper of an sbv_blocks handle."""
+    """Owning wrapper of an sbv_blocks handle.  Its sizes are read from the
+    library on every access (sbv_fit with rebuild rounds changes them)."""
 
     def __init__(self, handle):
         self.handle = C.c_void_p(handle)
+        self._info()
+
+    def _info(self):
         n, d, K, nnz = C.c_int64(), C.c_int32(), C.c_int64(), C.c_int64()
         _check(lib().sbv_blocks_info(self.handle, C.byref(n), C.byref(d), C.byref(K), C.byref(nnz)))
-        self.n, self.d, self.K, self.nnz = n.value, d.value, K.value, nnz.value
+        return n.value, d.value, K.value, nnz.value
+
+    n = property(lambda self: self._info()[0])
+    d = property(lambda self: self._info()[1])
+    K = property(lambda self: self._info()[2])
+    nnz = property(lambda self: self._info()[3])
 
     def free(self):
         if self.handle is not None and self.handle.value:
@@ -176,12 +185,13 @@ def sbv_build_blocks(X, y, beta_build, n_blocks, m, method=SBV_KMEANS, lloyd_ite
 
 
 def sbv_blocks_export(b):
-    bp = np.empty(b.K + 1, np.int64)
-    pts = np.empty(b.n, np.int64)
-    npt = np.empty(b.K + 1, np.int64)
-    nid = np.empty(max(b.nnz, 1), np.int64)
+    n, _, K, nnz = b._info()
+    bp = np.empty(K + 1, np.int64)
+    pts = np.empty(n, np.int64)
+    npt = np.empty(K + 1, np.int64)
+    nid = np.empty(max(nnz, 1), np.int64)
     _check(lib().sbv_blocks_export(b.handle, _p(bp, _i64), _p(pts, _i64), _p(npt, _i64), _p(nid, _i64)))
-    return bp, pts, npt, nid[:b.nnz]
+    return bp, pts, npt, nid[:nnz]
 
 
 def sbv_blocks_set_y(b, y):
@@ -275,7 +285,7 @@ def sbv_blocks_free(b):
 
 
 def sbv_blocks_info(b):
-    return b.n, b.d, b.K, b.nnz
+    return b._info()
 
 
 def sbv_last_error():
@@ -323,9 +333,9 @@ OBJECTIVE = C.CFUNCTYPE(C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_double)
 
 
 def make_fit_opts(optimizer=SBV_LBFGS, prec=SBV_FP64, fp64_polish=False, max_evals=500, ftol=1e-12, gtol=1e-6,
-                  lbfgs_m=10, init_step=0.5, checkpoint_path=None):
+                  lbfgs_m=10, init_step=0.5, checkpoint_path=None, rebuild_rounds=0):
     return sbv_fit_opts(int(optimizer), int(prec), int(bool(fp64_polish)), int(max_evals), float(ftol), float(gtol),
-                        0, int(lbfgs_m), float(init_step),
+                        int(rebuild_rounds), int(lbfgs_m), float(init_step),
                         checkpoint_path.encode() if checkpoint_path else None)
 
 

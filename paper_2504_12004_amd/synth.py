@@ -12,6 +12,8 @@ Workloads (inputs uniform on [0,1]^d as in Sec. 7.1 and Sec. 8):
   uneven_1m    n = 1,000,000, d = 10, Matern-5/2, ranges log-uniform on
                [0.05, 3], sigma^2 = 1, tau^2 = 1e-4, 50,000 k-means blocks
                bounded to 5..60 points, m = 200, 100 perturbed theta (seed 1/2)
+  (m_gen, gen_bs_mean, gen_max_bs: the independent generating structure of the
+  observations -- conditioning count, mean and largest block size)
   multi64      64 datasets, n ~ U[50k, 400k], d in {5,10,20}, nu in {3/2,5/2},
                m in {100,200,400} (seed 3)
   grad_5m      n = 5,000,000, d = 10, 250,000 blocks, m = 400 (seed 4)
@@ -23,9 +25,10 @@ SMALL_BETA = np.array([0.05, 0.1, 0.2, 0.3, 0.5, 0.8, 1.0, 1.5, 2.0, 3.0])
 
 WORKLOADS = {
     "small_fp64": dict(seed=0, n=20_000, d=10, two_nu=5, sigma2=1.0, tau2=1e-6, K=1_000, m=60,
-                       lloyd_iters=10, min_bs=0, max_bs=0),
+                       lloyd_iters=10, min_bs=0, max_bs=0, m_gen=120, gen_bs_mean=20, gen_max_bs=40),
     "uneven_1m": dict(seed=1, n=1_000_000, d=10, two_nu=5, sigma2=1.0, tau2=1e-4, K=50_000, m=200,
-                      lloyd_iters=10, min_bs=5, max_bs=60, n_theta=100, theta_seed=2),
+                      lloyd_iters=10, min_bs=5, max_bs=60, n_theta=100, theta_seed=2,
+                      m_gen=250, gen_bs_mean=10, gen_max_bs=22),
     "grad_5m": dict(seed=4, n=5_000_000, d=10, two_nu=5, sigma2=1.0, tau2=1e-4, K=250_000, m=400,
                     lloyd_iters=5, min_bs=5, max_bs=60),
     "warm_20m": dict(seed=6, n=20_000_000, d=10, two_nu=5, K=1_000_000, m=400, lloyd_iters=2,

@@ -82,3 +82,41 @@ def test_builder_rejects_bad_arguments(sbv):
     Xn[3, 1] = np.nan
     with pytest.raises(sbv.SBVError):
         sbv.sbv_build_blocks(Xn, None, [1.0, 1.0, 1.0], 10, 5)
+
+
+def test_builder_neighbours_at_full_size(sbv):
+    """The n = 1e6 (d = 10, K = 5e4 bounded to 5..60, m = 200) structure the
+    benchmark times: for 200 blocks spread over the rank order, the
+    neighbour set equals numpy brute force over every earlier point (ties
+    within 1e-12 relative of the m-th distance accepted either way)."""
+    from paper_2504_12004_amd import synth
+    w = synth.dataset("uneven_1m")
+    X, th = w["X"], w["theta"]
+    bb = np.exp(th[:10])
+    B = sbv.sbv_build_blocks(X, None, bb, w["K"], w["m"], method=sbv.SBV_KMEANS, lloyd_iters=w["lloyd_iters"],
+                             min_bs=w["min_bs"], max_bs=w["max_bs"], seed=w["seed"])
+    S = _structure(sbv, B)
+    B.free()
+    sizes = np.diff(S.block_ptr)
+    assert sizes.min() >= w["min_bs"] and sizes.max() <= w["max_bs"]
+    Zo = (X / bb)[S.block_pts]  # scaled points in rank order
+    rng = np.random.default_rng(8)
+    picks = np.unique(np.r_[1, 2, 7, S.K - 1, rng.integers(1, S.K, 196)])
+    pos = np.empty(len(X), np.int64)
+    pos[S.block_pts] = np.arange(len(X))
+    for r in picks:
+        b0, b1 = S.block_ptr[r], S.block_ptr[r + 1]
+        J = S.nn_idx[S.nn_ptr[r]:S.nn_ptr[r + 1]]
+        mm = min(w["m"], b0)
+        assert len(J) == mm
+        c = Zo[b0:b1].mean(0)
+        d2 = ((Zo[:b0] - c) ** 2).sum(1)
+        kth = np.partition(d2, mm - 1)[mm - 1]
+        pj = pos[J]
+        assert np.all(pj < b0), r  # strictly earlier blocks
+        assert len(np.unique(pj)) == mm
+        dj = ((Zo[pj] - c) ** 2).sum(1)
+        assert np.all(dj <= kth * (1 + 1e-12)), r
+        # everything strictly closer than the m-th distance is in the set
+        inside = np.nonzero(d2 < kth * (1 - 1e-12))[0]
+        assert set(inside.tolist()) <= set(pj.tolist()), r

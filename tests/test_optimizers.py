@@ -74,3 +74,27 @@ def test_checkpoint_resume_follows_the_same_trajectory(tmp_path, method):
     rest = sbv.make_fit_opts(optimizer=method, max_evals=150, ftol=1e-13, gtol=1e-7, checkpoint_path=ck)
     xb, fb, nb, _ = sbv.sbv_minimize(method, x0, negll, rest)
     assert np.array_equal(xa, xb) and fa == fb
+
+
+@pytest.mark.parametrize("method", [sbv.SBV_LBFGS, sbv.SBV_NELDER_MEAD])
+def test_non_finite_objective_is_backed_away_from(method):
+    """An objective that is +inf (or NaN) outside its domain, as the
+    log-likelihood is at a point where a block is not positive definite:
+    both optimisers treat such points as worse than any finite value and still
+    reach the minimum inside the domain (the first L-BFGS step from x0 = 0
+    overshoots the boundary just past the minimum)."""
+    calls = {"bad": 0}
+
+    def f(x, want_grad):
+        if x[0] > 0.9 or x[1] < -1.0:
+            calls["bad"] += 1
+            v = np.inf if x[0] > 0.9 else np.nan
+            return (v, np.zeros(2)) if want_grad else v
+        v = 1.0 + 100.0 * (x[0] - 0.85) ** 2 + (x[1] - 0.5) ** 2
+        if want_grad:
+            return v, np.array([200.0 * (x[0] - 0.85), 2.0 * (x[1] - 0.5)])
+        return v
+    o = sbv.make_fit_opts(optimizer=method, max_evals=3000, ftol=1e-13, gtol=1e-9, init_step=4.0)
+    x, fb, ne, conv = sbv.sbv_minimize(method, np.zeros(2), f, o)
+    assert conv and calls["bad"] > 0 and abs(fb - 1.0) < 1e-9
+    assert np.max(np.abs(x - [0.85, 0.5])) < 1e-5, x
