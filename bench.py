@@ -99,9 +99,9 @@ def main():
     # per size bucket, pick the fastest kernel variant and schedule (setup, not timed)
     tuned, sched = {}, {}
     for name, prec in (("fp64", sbv.SBV_FP64), ("fp32", sbv.SBV_FP32)):
-        ch, la = sbv.sbv_autotune([B], theta_true, two_nu, prec, reps=3, with_schedule=True)
+        ch, la, wv = sbv.sbv_autotune([B], theta_true, two_nu, prec, reps=3, with_schedule=True)
         tuned[name] = [int(t) for t in ch]
-        sched[name] = ["lookahead" if x else "plain" for x in la]
+        sched[name] = [("lookahead" if x else "plain") + f"/{int(v)}w" for x, v in zip(la, wv)]
     log(f"autotuned tiles per bucket: {tuned}, schedules {sched}")
 
     thetas = synth.perturbed_thetas(theta_true, w["n_theta"], w["theta_seed"])

@@ -278,17 +278,20 @@ sbv_status sbv_eval_graph_dev(const sbv_blocks* sets, int32_t n_sets, const doub
 
 /*
  * Autotuner: for every size bucket of the sets' plan, time `reps` launches of
- * each kernel variant able to hold the bucket's joint sizes, with and without
- * the lookahead schedule (the next diagonal tile factored during the current
- * trailing update), at theta (host, packed per set) and precision prec, and
- * keep the fastest for later evaluations.
+ * each kernel variant able to hold the bucket's joint sizes (tile capacity and
+ * wave count), with and without the lookahead schedule (the next diagonal tile
+ * factored during the current trailing update), at theta (host, packed per
+ * set) and precision prec, and keep the fastest for later evaluations.
  * chosen_tiles (optional, 16 entries) receives the chosen tile capacity per
  * bucket, longest bucket first; chosen_lookahead (optional, 16 entries) 1
  * where the lookahead schedule won, else 0 (always 0 for the large-block
- * bucket, which has a single schedule).  Synchronous.
+ * bucket, which has a single schedule); chosen_waves (optional, 16 entries)
+ * the waves per workgroup of the chosen kernel (16-wave kernels exist for
+ * FP32 only).  Synchronous.
  */
 sbv_status sbv_autotune(const sbv_blocks* sets, int32_t n_sets, const int32_t* two_nu, const double* theta,
-                        int32_t prec, int32_t reps, int32_t* chosen_tiles, int32_t* chosen_lookahead);
+                        int32_t prec, int32_t reps, int32_t* chosen_tiles, int32_t* chosen_lookahead,
+                        int32_t* chosen_waves);
 
 /* Number of blocks recomputed in FP64 by the last SBV_FP32 evaluation of this
  * handle (synchronises the device). */

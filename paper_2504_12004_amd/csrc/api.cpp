@@ -762,7 +762,8 @@ sbv_status sbv_sample(sbv_blocks h, const double* theta, int32_t two_nu, const d
 // ---- autotuner: per size bucket, time every kernel variant that can hold the
 // bucket's largest joint size and keep the fastest.
 sbv_status sbv_autotune(const sbv_blocks* sets, int32_t n_sets, const int32_t* two_nu, const double* theta,
-                        int32_t prec, int32_t reps, int32_t* chosen_tiles, int32_t* chosen_lookahead) {
+                        int32_t prec, int32_t reps, int32_t* chosen_tiles, int32_t* chosen_lookahead,
+                        int32_t* chosen_waves) {
   sbv_status st = check_sets(sets, n_sets, two_nu);
   if (st) return st;
   if (!theta || reps <= 0) return fail(SBV_E_INVAL, "theta and reps > 0 are required");
@@ -779,6 +780,7 @@ sbv_status sbv_autotune(const sbv_blocks* sets, int32_t n_sets, const int32_t* t
     if (B.large) {  // one kernel pair, nothing to choose
       if (chosen_tiles) chosen_tiles[bi] = kLargeNTM + kMaxPrefix;
       if (chosen_lookahead) chosen_lookahead[bi] = 0;
+      if (chosen_waves) chosen_waves[bi] = 8;
       ++bi;
       continue;
     }
@@ -809,6 +811,8 @@ sbv_status sbv_autotune(const sbv_blocks* sets, int32_t n_sets, const int32_t* t
     B.la[pk] = bestla;
     if (chosen_tiles) chosen_tiles[bi] = variant(bestv).ntm;
     if (chosen_lookahead) chosen_lookahead[bi] = bestla ? 1 : 0;
+    // (FP64 requests for a 16-wave variant run the 8-wave kernel)
+    if (chosen_waves) chosen_waves[bi] = (pk == 0 && variant(bestv).nw > 8) ? 8 : variant(bestv).nw;
     ++bi;
   }
   (void)hipEventDestroy(a);

@@ -1929,7 +1929,12 @@ __global__ __launch_bounds__(NW * 64) void k_block_contract_stream(const SetDesc
 }
 
 // ---- variants -------------------------------------------------------------
-static const Variant kVariants[] = {{4, 2}, {8, 4}, {12, 8}, {14, 8}, {16, 8}, {17, 8}};
+// Sorted by tile capacity; for a capacity, the 8-wave kernel comes first (the
+// default), the 16-wave one after it (FP32 only: more waves per SIMD to hide
+// latency, 128 registers each; the FP64 tiles do not fit 128 registers, so an
+// FP64 request for it runs the 8-wave kernel).  The autotuner may pick any
+// variant at or above a bucket's smallest fitting one.
+static const Variant kVariants[] = {{4, 2}, {8, 4}, {12, 8}, {14, 8}, {14, 16}, {16, 8}, {16, 16}, {17, 8}};
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
 int n_variants() { return kNumVariants; }
@@ -1940,24 +1945,38 @@ int variant_for(int nA) {
   return -1;
 }
 
+// Waves of the kernel actually launched for a variant: 16-wave variants exist
+// for FP32 only, and the gradient, contraction and simulation kernels always
+// use the 8-wave layout.
+template <typename T, int NW>
+constexpr int nw_of() {
+  return (NW > 8 && sizeof(T) == 8) ? 8 : NW;
+}
+
 template <typename T, int NTM, int NW>
 static hipError_t launch_t(int grid, bool grad, bool la, const SetDesc* sets, const double* theta,
                            const WorkItem* items, const int* count, double piv_tau, hipStream_t s) {
-  if (la && !grad)
-    hipLaunchKernelGGL((k_block_loglik<T, NTM, NW, false, false, true>), dim3(grid), dim3(NW * 64), 0, s, sets,
-                       theta, items, count, piv_tau, LargeArgs{});
-  else if (grad)
-    hipLaunchKernelGGL((k_block_loglik<T, NTM, NW, true>), dim3(grid), dim3(NW * 64), 0, s, sets, theta, items,
-                       count, piv_tau, LargeArgs{});
-  else
-    hipLaunchKernelGGL((k_block_loglik<T, NTM, NW, false>), dim3(grid), dim3(NW * 64), 0, s, sets, theta, items,
-                       count, piv_tau, LargeArgs{});
-  return hipGetLastError();
+  if constexpr (nw_of<T, NW>() != NW) {
+    return launch_t<T, NTM, nw_of<T, NW>()>(grid, grad, la, sets, theta, items, count, piv_tau, s);
+  } else {
+    constexpr int NWG = NW > 8 ? 8 : NW;  // the gradient kernels keep the 8-wave layout
+    if (la && !grad)
+      hipLaunchKernelGGL((k_block_loglik<T, NTM, NW, false, false, true>), dim3(grid), dim3(NW * 64), 0, s, sets,
+                         theta, items, count, piv_tau, LargeArgs{});
+    else if (grad)
+      hipLaunchKernelGGL((k_block_loglik<T, NTM, NWG, true>), dim3(grid), dim3(NWG * 64), 0, s, sets, theta, items,
+                         count, piv_tau, LargeArgs{});
+    else
+      hipLaunchKernelGGL((k_block_loglik<T, NTM, NW, false>), dim3(grid), dim3(NW * 64), 0, s, sets, theta, items,
+                         count, piv_tau, LargeArgs{});
+    return hipGetLastError();
+  }
 }
 
 template <typename T, int NTM, int NW>
 static hipError_t launch_s(int grid, const SetDesc* sets, const double* theta, const WorkItem* items,
                            const int* count, hipStream_t s) {
+  if constexpr (NW > 8) return launch_s<T, NTM, 8>(grid, sets, theta, items, count, s);
   hipLaunchKernelGGL((k_block_loglik<T, NTM, NW, false, true>), dim3(grid), dim3(NW * 64), 0, s, sets, theta,
                      items, count, 0.0, LargeArgs{});
   return hipGetLastError();
@@ -1966,6 +1985,7 @@ static hipError_t launch_s(int grid, const SetDesc* sets, const double* theta, c
 template <typename T, int NTM, int NW>
 static hipError_t launch_c(int grid, const SetDesc* sets, const double* theta, const WorkItem* items,
                            const int* count, hipStream_t s) {
+  if constexpr (NW > 8) return launch_c<T, NTM, 8>(grid, sets, theta, items, count, s);
   hipLaunchKernelGGL((k_block_contract<T, NTM, NW>), dim3(grid), dim3(NW * 64), 0, s, sets, theta, items, count);
   return hipGetLastError();
 }
@@ -1976,8 +1996,10 @@ static hipError_t launch_c(int grid, const SetDesc* sets, const double* theta, c
     case 1: return CALL(T, 8, 4);     \
     case 2: return CALL(T, 12, 8);    \
     case 3: return CALL(T, 14, 8);    \
-    case 4: return CALL(T, 16, 8);    \
-    case 5: return CALL(T, 17, 8);    \
+    case 4: return CALL(T, 14, 16);   \
+    case 5: return CALL(T, 16, 8);    \
+    case 6: return CALL(T, 16, 16);   \
+    case 7: return CALL(T, 17, 8);    \
   }
 
 hipError_t launch_loglik(int prec, int v, int grid, const SetDesc* sets, const double* theta,

@@ -98,7 +98,7 @@ def lib():
         "sbv_features": (C.c_int, [_d, _d, C.c_int64, C.c_int32, C.c_int64, C.c_uint64, _d]),
         "sbv_eval_graph_dev": (C.c_int, [C.POINTER(_h), C.c_int32, C.c_void_p, _i32, C.c_int32, C.c_int32,
                                          C.c_void_p, C.c_void_p, C.c_void_p]),
-        "sbv_autotune": (C.c_int, [C.POINTER(_h), C.c_int32, _i32, _d, C.c_int32, C.c_int32, _i32, _i32]),
+        "sbv_autotune": (C.c_int, [C.POINTER(_h), C.c_int32, _i32, _d, C.c_int32, C.c_int32, _i32, _i32, _i32]),
         "sbv_timing_enable": (C.c_int, [C.c_int32]),
         "sbv_timing_read": (C.c_int, [C.c_int32, _i32, _d, _i64]),
         "sbv_plan_flops": (C.c_int, [C.POINTER(_h), C.c_int32, _i32, _d, _i32, _i32]),
@@ -482,13 +482,16 @@ def sbv_eval_graph_dev(sets, theta_dev, two_nu, out_dev, prec=SBV_FP64, grad_dev
 
 def sbv_autotune(sets, theta, two_nu, prec=SBV_FP64, reps=2, with_schedule=False):
     """Chosen tile capacity per size bucket; with_schedule=True also returns
-    the per-bucket lookahead choice (1 = lookahead schedule)."""
+    the per-bucket lookahead choice (1 = lookahead schedule) and the waves per
+    workgroup of the chosen kernel."""
     hs, ns = _handles(sets)
     th = _c64(np.concatenate([np.ravel(t) for t in theta]) if isinstance(theta, (list, tuple)) else theta)
     tn = np.ascontiguousarray(np.broadcast_to(np.asarray(two_nu, np.int32), (ns,)), dtype=np.int32)
     ch = np.zeros(16, np.int32)
     la = np.zeros(16, np.int32)
-    _check(lib().sbv_autotune(hs, ns, _p(tn, _i32), _p(th), int(prec), int(reps), _p(ch, _i32), _p(la, _i32)))
+    wv = np.zeros(16, np.int32)
+    _check(lib().sbv_autotune(hs, ns, _p(tn, _i32), _p(th), int(prec), int(reps), _p(ch, _i32), _p(la, _i32),
+                              _p(wv, _i32)))
     if with_schedule:
-        return ch[ch > 0], la[ch > 0]
+        return ch[ch > 0], la[ch > 0], wv[ch > 0]
     return ch[ch > 0]
