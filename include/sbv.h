@@ -173,6 +173,52 @@ sbv_status sbv_sample(sbv_blocks h, const double* theta, int32_t two_nu, const d
 sbv_status sbv_sample_dev(sbv_blocks h, const double* theta_dev, int32_t two_nu, const double* xi_dev,
                           double* y_dev, void* stream);
 
+/* ---- prediction (Sec. 5.5 GP Prediction; Sec. 4.2 predictive product) ----
+ * New inputs X* are grouped into prediction blocks B*_j; each block takes the
+ * m_pred observed points nearest its centroid (in beta_build-scaled space,
+ * exact search over every observed point) as NN(B*_j), and
+ *   p(y* | y) ~ prod_j p(y_{B*_j} | y_{NN(B*_j)}).
+ * For every block, Alg. 5 Step 1 on [NN(B*_j); B*_j] gives the conditional mean
+ * mu_new and covariance Sigma_new; the library reports mu_new and the
+ * predictive variance diag(Sigma_new) of a new observation (the nugget is on
+ * Sigma_new's diagonal).  A prediction structure refers to its observed
+ * handle, which must outlive it; predictions use the handle's current
+ * observations.  Joint sizes m_pred + |B*_j| are limited to 272.
+ */
+typedef struct sbv_pred_s* sbv_pred;
+
+/* Build a prediction structure: X* (host, row-major n_pred x d) clustered as
+ * sbv_build_blocks does (opts; no conditioning among new points), then the
+ * m_pred nearest observed points of each block.  n_blocks <= n_pred. */
+sbv_status sbv_pred_build(sbv_blocks h, const double* Xp, int64_t n_pred, const double* beta_build,
+                          int64_t n_blocks, int32_t m_pred, const sbv_build_opts* opts, sbv_pred* out);
+
+/* Explicit prediction structure (exchange format): block_ptr (K+1) and
+ * block_pts (n_pred) list the blocks as ids of X*; nn_ptr (K+1) and nn_idx
+ * list each block's conditioning points as observed ids (original order of the
+ * handle's points).  Bad ids, a non-permutation or a joint size above 272:
+ * SBV_E_INVAL. */
+sbv_status sbv_pred_import(sbv_blocks h, const double* Xp, int64_t n_pred, int64_t K, const int64_t* block_ptr,
+                           const int64_t* block_pts, const int64_t* nn_ptr, const int64_t* nn_idx, sbv_pred* out);
+sbv_status sbv_pred_info(sbv_pred p, int64_t* n_pred, int64_t* K, int64_t* nnz_nn);
+sbv_status sbv_pred_export(sbv_pred p, int64_t* block_ptr, int64_t* block_pts, int64_t* nn_ptr, int64_t* nn_idx);
+void sbv_pred_free(sbv_pred p); /* NULL-safe */
+
+/* Predictive means and variances at theta (host, d+2 log-parameters): mean and
+ * var are host arrays of n_pred values in the order of X*.  A block that is
+ * not positive definite in FP64 gives NaN for its points and SBV_E_NOTPD. */
+sbv_status sbv_predict(sbv_pred p, const double* theta, int32_t two_nu, double* mean, double* var);
+
+/* Conditional simulation of predictions (Sec. 5.5): n_draws draws per point
+ * from N(mean_j, var_j) with the caller's standard-normal innovations xi_dev
+ * (device, n_draws x n_pred, draw-major), summarised on the device as
+ * stats_dev (4 n_pred values: sample means, sample variances with divisor
+ * n_draws - 1, then the lower and upper ends of the 95 % interval
+ * mean -/+ 1.959964 sd).  mean_dev, var_dev: device, n_pred.  Asynchronous on
+ * `stream`. */
+sbv_status sbv_predict_draws_dev(const double* mean_dev, const double* var_dev, int64_t n_pred, const double* xi_dev,
+                                 int32_t n_draws, double* stats_dev, void* stream);
+
 /* Options of the maximum-likelihood driver. */
 typedef struct {
   int32_t optimizer;          /* SBV_NELDER_MEAD (values only) or SBV_LBFGS (values + gradients)   */

@@ -42,6 +42,10 @@ def lib():
                                             _d, C.c_int, _d, _d, _d, C.c_int, _d]
         L.sbv_oracle_sample.argtypes = [_d, C.c_int64, C.c_int, C.c_int64, _i64, _i64, _i64, _i64, _d,
                                         C.c_int, _d, _d]
+        L.sbv_oracle_predict.argtypes = [_d, _d, C.c_int64, C.c_int, _d, C.c_int64, C.c_int64, _i64, _i64, _i64,
+                                         _i64, _d, C.c_int, _d, _d]
+        L.sbv_oracle_pred_neighbours.argtypes = [_d, C.c_int64, C.c_int, _d, C.c_int64, _i64, _i64, _d, C.c_int,
+                                                 _i64]
         if hasattr(L, "mlp_oracle_forward"):
             L.mlp_oracle_forward.argtypes = [_d, C.c_int, _d, C.c_int, C.c_int, C.c_int, C.c_int, _d, _d]
             L.mlp_oracle_loss_grad.restype = C.c_double
@@ -229,3 +233,47 @@ def features(X, y, sub):
     if st:
         raise ValueError("oracle features rejected its arguments")
     return f
+
+
+def pred_structure(X, Xp, beta_build, K, m, lloyd_iters=10, min_bs=0, max_bs=0, seed=0):
+    """Prediction structure: blocks of the new points Xp (the oracle builder's
+    clustering with no conditioning) and, per block, the m observed points of X
+    nearest its centroid.  Returned as a Structure over Xp's ids whose nn_idx
+    are observed ids."""
+    B = build(Xp, beta_build, K, 0, lloyd_iters=lloyd_iters, min_bs=min_bs, max_bs=max_bs, seed=seed)
+    X, Xp, bb = _c64(X), _c64(Xp), _c64(beta_build)
+    mm = min(int(m), X.shape[0])
+    nid = np.empty(max(B.K * mm, 1), np.int64)
+    st = lib().sbv_oracle_pred_neighbours(_p(X), X.shape[0], X.shape[1], _p(Xp), B.K, _p(B.block_ptr, _i64),
+                                          _p(B.block_pts, _i64), _p(bb), int(m), _p(nid, _i64))
+    if st:
+        raise ValueError("oracle pred_neighbours rejected its arguments")
+    return Structure(Xp.shape[0], X.shape[1], mm, B.block_ptr, B.block_pts, np.arange(B.K + 1) * mm,
+                     nid[:B.K * mm])
+
+
+def predict(X, y, Xp, P, theta, two_nu):
+    """Predictive means and variances diag(Sigma_new) of the new points (Alg. 5
+    Step 1 per prediction block), in the order of Xp."""
+    X, y, Xp, th = _c64(X), _c64(y), _c64(Xp), _c64(theta)
+    mean = np.empty(Xp.shape[0])
+    var = np.empty(Xp.shape[0])
+    st = lib().sbv_oracle_predict(_p(X), _p(y), X.shape[0], X.shape[1], _p(Xp), Xp.shape[0], P.K,
+                                  _p(P.block_ptr, _i64), _p(P.block_pts, _i64), _p(P.nn_ptr, _i64),
+                                  _p(P.nn_idx if len(P.nn_idx) else np.zeros(1, np.int64), _i64), _p(th),
+                                  int(two_nu), _p(mean), _p(var))
+    if st == OR_EINVAL:
+        raise ValueError("oracle predict rejected its arguments")
+    return mean, var
+
+
+def pred_draws(mean, var, xi):
+    """Conditional simulation of predictions (Sec. 5.5): draws mean + sqrt(var) xi
+    (xi: n_draws x n_pred), their sample mean and variance (divisor n_draws - 1)
+    and the 95 % interval sample mean -/+ z_{0.025} sample sd."""
+    from scipy.stats import norm
+    draws = np.asarray(mean)[None, :] + np.sqrt(np.asarray(var))[None, :] * np.asarray(xi)
+    m = draws.mean(axis=0)
+    v = draws.var(axis=0, ddof=1)
+    z = norm.ppf(0.975)
+    return m, v, m - z * np.sqrt(v), m + z * np.sqrt(v)

@@ -803,3 +803,100 @@ int sbv_oracle_sample(const double* X, int64_t n, int d, int64_t K, const int64_
   }
   return OR_OK;
 }
+
+/* ------------------------------------------------------------------------- */
+/* Prediction, Sec. 5.5 (GP Prediction) with the block-conditional predictive
+ * distribution of Sec. 4.2: every prediction block B* conditions on its
+ * neighbours NN(B*) among the observed points, and Alg. 5 Step 1 gives
+ *   mu_new    = Sigma'cross^T y'_J            (Sigma'cross = L^{-1} K(J, B*),
+ *   Sigma_new = K(B*, B*) - Sigma'cross^T Sigma'cross     y'_J = L^{-1} y_J,
+ *                                                          L = chol K(J, J)).
+ * The predictive variance of a new observation is diag(Sigma_new); the nugget
+ * sits on the diagonal of K(B*, B*) (reading R2), none on K(J, B*).
+ * Xp: n_pred x d new inputs; the structure lists prediction blocks as ids of
+ * Xp (block_ptr, block_pts) and their neighbours as observed ids (nn_ptr,
+ * nn_idx).  mean and var are indexed by prediction id. */
+int sbv_oracle_predict(const double* X, const double* y, int64_t n, int d, const double* Xp, int64_t n_pred,
+                       int64_t K, const int64_t* block_ptr, const int64_t* block_pts, const int64_t* nn_ptr,
+                       const int64_t* nn_idx, const double* theta, int two_nu, double* mean, double* var) {
+  if (n <= 0 || n_pred <= 0 || d <= 0 || d > 64 || K <= 0) return OR_EINVAL;
+  if (two_nu != 1 && two_nu != 3 && two_nu != 5 && two_nu != 7) return OR_EINVAL;
+  if (block_ptr[0] != 0 || block_ptr[K] > n_pred || nn_ptr[0] != 0) return OR_EINVAL;
+  for (int64_t r = 0; r < K; ++r) {
+    if (block_ptr[r + 1] <= block_ptr[r] || nn_ptr[r + 1] < nn_ptr[r]) return OR_EINVAL;
+    for (int64_t t = block_ptr[r]; t < block_ptr[r + 1]; ++t)
+      if (block_pts[t] < 0 || block_pts[t] >= n_pred) return OR_EINVAL;
+    for (int64_t t = nn_ptr[r]; t < nn_ptr[r + 1]; ++t)
+      if (nn_idx[t] < 0 || nn_idx[t] >= n) return OR_EINVAL;
+  }
+  double beta[64];
+  for (int k = 0; k < d; ++k) beta[k] = exp(theta[k]);
+  double s2 = exp(theta[d]), t2 = exp(theta[d + 1]);
+  int bad = 0;
+#pragma omp parallel for schedule(dynamic, 4) reduction(| : bad)
+  for (int64_t r = 0; r < K; ++r) {
+    const int64_t mi = nn_ptr[r + 1] - nn_ptr[r], bi = block_ptr[r + 1] - block_ptr[r];
+    const int64_t* J = nn_idx + nn_ptr[r];
+    const int64_t* P = block_pts + block_ptr[r];
+    double* Scon = (double*)malloc(sizeof(double) * (mi * mi + 1));
+    double* Slk = (double*)malloc(sizeof(double) * (bi * bi + 1));
+    double* Scross = (double*)malloc(sizeof(double) * (mi * bi + 1));
+    double* yJ = (double*)malloc(sizeof(double) * (mi + 1));
+    /* Sigma^lk = K(B*, B*), Sigma^con = K(J, J), Sigma^cross = K(J, B*) */
+    for (int64_t a = 0; a < bi; ++a)
+      for (int64_t b = 0; b < bi; ++b)
+        Slk[a * bi + b] = or_cov(Xp + P[a] * d, Xp + P[b] * d, d, beta, s2, t2, two_nu, a == b);
+    for (int64_t a = 0; a < mi; ++a)
+      for (int64_t b = 0; b < mi; ++b)
+        Scon[a * mi + b] = or_cov(X + J[a] * d, X + J[b] * d, d, beta, s2, t2, two_nu, a == b);
+    for (int64_t a = 0; a < mi; ++a)
+      for (int64_t b = 0; b < bi; ++b)
+        Scross[a * bi + b] = or_cov(X + J[a] * d, Xp + P[b] * d, d, beta, s2, t2, two_nu, 0);
+    for (int64_t a = 0; a < mi; ++a) yJ[a] = y[J[a]];
+    int st = 0;
+    /* L <- POTRF(Sigma^con); Sigma'^cross <- TRSM; y'_J <- TRSV */
+    if (mi > 0 && or_chol(Scon, mi)) st = 1;
+    if (!st && mi > 0) { or_trsm_lower(Scon, mi, Scross, bi); or_trsm_lower(Scon, mi, yJ, 1); }
+    for (int64_t a = 0; a < bi; ++a) {
+      double mu = 0.0, c = 0.0;
+      for (int64_t k = 0; k < mi; ++k) {
+        mu += Scross[k * bi + a] * yJ[k];
+        c += Scross[k * bi + a] * Scross[k * bi + a];
+      }
+      mean[P[a]] = st ? NAN : mu;
+      var[P[a]] = st ? NAN : Slk[a * bi + a] - c;
+    }
+    if (st) bad = 1;
+    free(Scon); free(Slk); free(Scross); free(yJ);
+  }
+  return bad ? OR_ENOTPD : OR_OK;
+}
+
+/* Neighbours of prediction blocks (Sec. 4.2, NN(B*) taken from the observed
+ * points): for every block of new points, the m observed points nearest the
+ * block centroid in beta_build-scaled space, brute force, ties to the lower
+ * observed id, sorted by (distance, id).  nn_idx: K x min(m, n) entries. */
+int sbv_oracle_pred_neighbours(const double* X, int64_t n, int d, const double* Xp, int64_t K,
+                               const int64_t* block_ptr, const int64_t* block_pts, const double* beta_build,
+                               int m, int64_t* nn_idx) {
+  if (n <= 0 || d <= 0 || d > 64 || K <= 0 || m < 0) return OR_EINVAL;
+  const int64_t mm = m < n ? m : n;
+  double* Z = (double*)malloc(sizeof(double) * n * d);
+  for (int64_t i = 0; i < n; ++i)
+    for (int k = 0; k < d; ++k) Z[i * d + k] = X[i * d + k] / beta_build[k];
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int64_t r = 0; r < K; ++r) {
+    double c[64] = {0};
+    const int64_t lo = block_ptr[r], hi = block_ptr[r + 1];
+    for (int64_t t = lo; t < hi; ++t)
+      for (int k = 0; k < d; ++k) c[k] += Xp[block_pts[t] * d + k] / beta_build[k];
+    for (int k = 0; k < d; ++k) c[k] /= (double)(hi - lo);
+    or_cand* cd = (or_cand*)malloc(sizeof(or_cand) * n);
+    for (int64_t p = 0; p < n; ++p) { cd[p].d2 = or_d2(Z + p * d, c, d); cd[p].pos = p; }
+    qsort(cd, (size_t)n, sizeof(or_cand), or_cand_cmp);
+    for (int64_t t = 0; t < mm; ++t) nn_idx[r * mm + t] = cd[t].pos;
+    free(cd);
+  }
+  free(Z);
+  return OR_OK;
+}

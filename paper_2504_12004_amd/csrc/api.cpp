@@ -513,6 +513,8 @@ sbv_status sbv_internal_view(sbv_blocks h, HandleView* v) {
   v->bucket_count = h->rl_count.data();
   v->items = h->rl_items.p;
   v->dcount = h->rl_dcount.p;
+  v->block_pts_host = h->block_pts.data();
+  v->n = h->n;
   return SBV_OK;
 }
 

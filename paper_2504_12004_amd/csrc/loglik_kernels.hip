@@ -169,7 +169,7 @@ constexpr int kChunk = 32;
 template <typename T>
 constexpr bool kLateCov = sizeof(T) == 8;
 
-template <typename T, int NTM, bool GRAD = false, bool LA = false>
+template <typename T, int NTM, bool GRAD = false, bool LA = false, bool SMP = false>
 struct Smem {
   static constexpr int kPanel = NTM * kOpT;
   static constexpr int kRhs = NTM * kTile * kRS;
@@ -193,6 +193,7 @@ struct Smem {
   unsigned long long prof[16];
 #endif
   T gv[GRAD ? NTM * kTile : 1];     // g = Q z_B accumulated over chunks (GRAD only)
+  T vacc[SMP ? NTM * kTile : 1];    // conditional simulation: sum of L_rc^2 over the block's columns
 };
 
 // 1/sqrt(p): hardware reciprocal square root refined by Newton steps
@@ -314,7 +315,7 @@ __device__ __forceinline__ float rows_sum(float v) {
 template <typename T, bool SAMPLE = false, class SM>
 __device__ __forceinline__ void factor_diag(SM& sm, T* negM_out, int lane, int k, int nreal, T diag0, T tau,
                                             T& pivot_out, T& z_out, int& bad, int& low, int mi = 0,
-                                            T* ysim = nullptr) {
+                                            T* ysim = nullptr, T* vacc = nullptr) {
   const int r = lane & 15, g = lane >> 4;
   T a[4], x[4];
 #pragma unroll
@@ -382,6 +383,19 @@ __device__ __forceinline__ void factor_diag(SM& sm, T* negM_out, int lane, int k
       }
       yr = (r == j) ? zj : (r > j ? yr - lrj * zj : yr);
     }
+  }
+  if (SAMPLE && vacc) {
+    // conditional variance of the block's rows of this tile: the within-tile
+    // part of sum over the block's columns c <= r of L[r][c]^2 (columns of
+    // earlier tiles were added by var_update)
+    T part = T(0);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int c = g + 4 * q;
+      if (c <= r && kTile * k + c >= mi) part += a[q] * a[q];
+    }
+    const T vs = rows_sum(part);
+    if (g == 0 && kTile * k + r >= mi) vacc[kTile * k + r] += vs;
   }
   if (!SAMPLE) {
     // z_k = L_kk^{-1} y_k = X y_k: lane (r, g) sums X[r][c] y[c] over its
@@ -630,6 +644,23 @@ __device__ __forceinline__ void load_prefix(SM& sm, int tid, int k, int nt, cons
   if (tid < kTile) sm.zk[tid] = zp[kTile * k + tid];
 }
 
+// Conditional simulation with variances: rows below tile k add the squares of
+// their entries of L in the block's columns of tile k (column tile k of L
+// staged in the panel); rows below a column of the block are block rows.
+template <typename T, class SM>
+__device__ __forceinline__ void var_update(SM& sm, int lane, int k, int nt, int mi) {
+  if (kTile * k + kTile <= mi) return;  // no column of the block in this tile
+  const int c0 = mi > kTile * k ? mi - kTile * k : 0;
+  for (int rho = kTile * (k + 1) + lane; rho < kTile * nt; rho += 64) {
+    T s = T(0);
+    for (int c = c0; c < kTile; ++c) {
+      const T v = sm.panel[kOpT * (rho >> 4) + opoff<T>(rho & 15, c)];
+      s += v * v;
+    }
+    sm.vacc[rho] += s;
+  }
+}
+
 // Panel wave: for every tile step factors the diagonal tile, solves the 16
 // entries of z, accumulates the trailing log-pivots and z^2 in FP64, and
 // applies the forward-solve update to the observations below.  In GRAD mode it
@@ -638,7 +669,7 @@ __device__ __forceinline__ void load_prefix(SM& sm, int tid, int k, int nt, cons
 template <typename T, int NTM, int NTHR, bool GRAD, bool SAMPLE, bool PRE, class SM>
 __device__ __forceinline__ void panel_wave(SM& sm, int lane, int nt, int mi, int nA, int d, int two_nu, T sigma2,
                                            T tau2, T tau, double& ld_acc, double& q_acc, int& bad, int& low,
-                                           double* yout, int p, const T* Wp, const T* zp) {
+                                           double* yout, int p, const T* Wp, const T* zp, double* vout = nullptr) {
   const T diag0 = sigma2 + tau2;
   SBV_PROF_DECL
   if (!kLateCov<T>) {
@@ -668,10 +699,16 @@ __device__ __forceinline__ void panel_wave(SM& sm, int lane, int nt, int mi, int
     // the serial diagonal factorisations are the critical path: they win issue
     // arbitration against the worker that shares this SIMD
     __builtin_amdgcn_s_setprio(2);
-    factor_diag<T, SAMPLE>(sm, sm.negM, lane, k, nA - kTile * k, diag0, tau, piv, zr, bad, low, mi, &ysim);
+    T* vacc = nullptr;
+    if constexpr (SAMPLE) vacc = vout ? sm.vacc : nullptr;
+    factor_diag<T, SAMPLE>(sm, sm.negM, lane, k, nA - kTile * k, diag0, tau, piv, zr, bad, low, mi, &ysim, vacc);
     __builtin_amdgcn_s_setprio(0);
     const int rowg = kTile * k + lane;
-    if (SAMPLE && lane < 16 && rowg >= mi && rowg < nA) yout[rowg - mi] = (double)ysim;
+    if (SAMPLE && lane < 16 && rowg >= mi && rowg < nA) {
+      yout[rowg - mi] = (double)ysim;
+      if constexpr (SAMPLE)
+        if (vout) vout[rowg - mi] = (double)sm.vacc[rowg];
+    }
     if (lane < 16) {
       sm.zk[lane] = zr;
       if (GRAD) sm.zfull[rowg] = zr;
@@ -685,6 +722,8 @@ __device__ __forceinline__ void panel_wave(SM& sm, int lane, int nt, int mi, int
     __syncthreads();  // S3: column k of L published
     SBV_PROF(3, true);
     y_update<T>(sm, lane, kTile * (k + 1), nt);
+    if constexpr (SAMPLE)
+      if (vout) var_update<T>(sm, lane, k, nt, mi);
     SBV_PROF(4, true);
   }
 }
@@ -1204,7 +1243,7 @@ __global__ __launch_bounds__(NW * 64) void k_block_loglik(const SetDesc* __restr
                                                           const int* __restrict__ count,
                                                           double piv_tau, LargeArgs L) {
   static_assert(!PRE || (!SAMPLE && !LA && NTM == kLargeNTM), "large-block mode: no simulation, no lookahead");
-  __shared__ Smem<T, NTM, GRAD, LA> sm;
+  __shared__ Smem<T, NTM, GRAD, LA, SAMPLE> sm;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -1274,7 +1313,10 @@ __global__ __launch_bounds__(NW * 64) void k_block_loglik(const SetDesc* __restr
       T v = T(0);
       if (real && (!SAMPLE || pa < mi)) v = T(S.y[pos]);
       sm.yv[pl] = v;
-      if (SAMPLE) sm.xi[pl] = (pa >= mi && real) ? T(S.xi[b0 + (pa - mi)]) : T(0);
+      if constexpr (SAMPLE) {
+        sm.xi[pl] = (pa >= mi && real && S.xi) ? T(S.xi[b0 - S.out_off + (pa - mi)]) : T(0);
+        sm.vacc[pl] = T(0);
+      }
     }
     if (tid == 0) sm.la_flag = -1;
     __syncthreads();
@@ -1289,9 +1331,10 @@ __global__ __launch_bounds__(NW * 64) void k_block_loglik(const SetDesc* __restr
         panel_wave_la<T, NTM, NW * 64>(sm, lane, nt, mi, nA, d, S.two_nu, sigma2, tau2, T(piv_tau), ld_acc, q_acc,
                                        bad, low);
       else
-        panel_wave<T, NTM, NW * 64, GRAD, SAMPLE, PRE>(sm, lane, nt, mil, nAl, d, S.two_nu, sigma2, tau2,
-                                                       T(piv_tau), ld_acc, q_acc, bad, low, S.y_out + b0, pre,
-                                                       Wp, zp);
+        panel_wave<T, NTM, NW * 64, GRAD, SAMPLE, PRE>(
+            sm, lane, nt, mil, nAl, d, S.two_nu, sigma2, tau2, T(piv_tau), ld_acc, q_acc, bad, low,
+            SAMPLE ? S.y_out + (b0 - S.out_off) : nullptr, pre, Wp, zp,
+            (SAMPLE && S.var_out) ? S.var_out + (b0 - S.out_off) : nullptr);
 #pragma unroll
       for (int off = 8; off >= 1; off >>= 1) {
         ld_acc += __shfl_xor(ld_acc, off, 16);

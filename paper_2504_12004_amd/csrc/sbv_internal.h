@@ -25,12 +25,14 @@ struct SetDesc {
   double* gradb;          // K x (d+2) per-block gradient terms (output, gradient kernels)
   double* qbuf;           // adjoint buffer: per block e, g, Q (elements of the kernel precision)
   const int64_t* qoff;    // K offsets into qbuf, in elements of the kernel precision
-  const double* xi;       // n innovations, rank order (conditional simulation only)
-  double* y_out;          // n simulated observations, rank order (conditional simulation only)
+  const double* xi;       // n innovations, rank order (conditional simulation only; null: all 0)
+  double* y_out;          // simulated observations, rank order (conditional simulation only)
+  double* var_out;        // conditional variances of the block points (prediction only; may be null)
   int32_t d;
   int32_t two_nu;
   int32_t theta_off;      // offset of this set's d+2 parameters in the theta buffer
   int32_t K;
+  int32_t out_off;        // xi, y_out and var_out are indexed by (ordered position - out_off)
 };
 
 // One unit of work: block `block` of set `set`.
@@ -138,11 +140,19 @@ struct HandleView {
   const int* bucket_count;        // host, n_buckets
   const WorkItem* items;          // device, K items grouped by bucket
   const int* dcount;              // device, n_buckets counts
+  const int64_t* block_pts_host;  // host, n: original id of each ordered position
+  int64_t n;
 };
 
 // Pivot threshold of the FP32 path (a block whose FP32 pivot falls to or
 // below this fraction of its original diagonal is recomputed in FP64).
 double fp32_pivot_tau();
+
+// Summaries of n_draws draws mean_j + sqrt(var_j) xi[t * n + j] per point j:
+// stats[j] sample mean, stats[n + j] sample variance (divisor n_draws - 1),
+// stats[2n + j] / stats[3n + j] the 95 % interval mean -/+ z sd.
+hipError_t launch_pred_draws(const double* mean, const double* var, int64_t n, const double* xi, int n_draws,
+                             double* stats, hipStream_t s);
 
 hipError_t launch_gather_y(const double* y_ord, const int32_t* pos_of, double* y, int64_t n, hipStream_t s);
 hipError_t launch_scatter_y(const double* y, const int32_t* pos_of, double* y_ord, int64_t n,

@@ -96,6 +96,15 @@ def lib():
         "sbv_mlp_save": (C.c_int, [_h, C.c_char_p]),
         "sbv_mlp_load": (C.c_int, [C.c_char_p, C.POINTER(_h)]),
         "sbv_features": (C.c_int, [_d, _d, C.c_int64, C.c_int32, C.c_int64, C.c_uint64, _d]),
+        "sbv_pred_build": (C.c_int, [_h, _d, C.c_int64, _d, C.c_int64, C.c_int32, C.POINTER(sbv_build_opts),
+                                     C.POINTER(_h)]),
+        "sbv_pred_import": (C.c_int, [_h, _d, C.c_int64, C.c_int64, _i64, _i64, _i64, _i64, C.POINTER(_h)]),
+        "sbv_pred_info": (C.c_int, [_h, _i64, _i64, _i64]),
+        "sbv_pred_export": (C.c_int, [_h, _i64, _i64, _i64, _i64]),
+        "sbv_pred_free": (None, [_h]),
+        "sbv_predict": (C.c_int, [_h, _d, C.c_int32, _d, _d]),
+        "sbv_predict_draws_dev": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int32, C.c_void_p,
+                                            C.c_void_p]),
         "sbv_eval_graph_dev": (C.c_int, [C.POINTER(_h), C.c_int32, C.c_void_p, _i32, C.c_int32, C.c_int32,
                                          C.c_void_p, C.c_void_p, C.c_void_p]),
         "sbv_autotune": (C.c_int, [C.POINTER(_h), C.c_int32, _i32, _d, C.c_int32, C.c_int32, _i32, _i32, _i32]),
@@ -495,3 +504,82 @@ def sbv_autotune(sets, theta, two_nu, prec=SBV_FP64, reps=2, with_schedule=False
     if with_schedule:
         return ch[ch > 0], la[ch > 0], wv[ch > 0]
     return ch[ch > 0]
+
+
+class Pred:
+    """Owning wrapper of an sbv_pred prediction structure (keeps its observed
+    handle alive)."""
+
+    def __init__(self, handle, blocks):
+        self.handle = C.c_void_p(handle)
+        self.blocks = blocks
+        n, K, nnz = C.c_int64(), C.c_int64(), C.c_int64()
+        _check(lib().sbv_pred_info(self.handle, C.byref(n), C.byref(K), C.byref(nnz)))
+        self.n_pred, self.K, self.nnz = n.value, K.value, nnz.value
+
+    def free(self):
+        if self.handle is not None and self.handle.value:
+            lib().sbv_pred_free(self.handle)
+        self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def sbv_pred_build(b, Xp, beta_build, n_blocks, m_pred, method=SBV_KMEANS, lloyd_iters=10, min_bs=0, max_bs=0,
+                   seed=0):
+    Xp = _c64(Xp)
+    bb = _c64(beta_build)
+    o = sbv_build_opts(int(method), int(lloyd_iters), int(min_bs), int(max_bs), 0, int(seed))
+    h = C.c_void_p()
+    _check(lib().sbv_pred_build(b.handle, _p(Xp), Xp.shape[0], _p(bb), int(n_blocks), int(m_pred), C.byref(o),
+                                C.byref(h)))
+    return Pred(h.value, b)
+
+
+def sbv_pred_import(b, Xp, block_ptr, block_pts, nn_ptr, nn_idx):
+    Xp = _c64(Xp)
+    bp, pts, npt, nid = _ci64(block_ptr), _ci64(block_pts), _ci64(nn_ptr), _ci64(nn_idx)
+    if len(nid) == 0:
+        nid = np.zeros(1, np.int64)
+    h = C.c_void_p()
+    _check(lib().sbv_pred_import(b.handle, _p(Xp), Xp.shape[0], len(bp) - 1, _p(bp, _i64), _p(pts, _i64),
+                                 _p(npt, _i64), _p(nid, _i64), C.byref(h)))
+    return Pred(h.value, b)
+
+
+def sbv_pred_export(p):
+    bp = np.empty(p.K + 1, np.int64)
+    pts = np.empty(p.n_pred, np.int64)
+    npt = np.empty(p.K + 1, np.int64)
+    nid = np.empty(max(p.nnz, 1), np.int64)
+    _check(lib().sbv_pred_export(p.handle, _p(bp, _i64), _p(pts, _i64), _p(npt, _i64), _p(nid, _i64)))
+    return bp, pts, npt, nid[:p.nnz]
+
+
+def sbv_pred_info(p):
+    return p.n_pred, p.K, p.nnz
+
+
+def sbv_pred_free(p):
+    p.free()
+
+
+def sbv_predict(p, theta, two_nu):
+    """Predictive means and variances (host arrays in the order of X*)."""
+    th = _c64(theta)
+    mean = np.empty(p.n_pred)
+    var = np.empty(p.n_pred)
+    _check(lib().sbv_predict(p.handle, _p(th), int(two_nu), _p(mean), _p(var)))
+    return mean, var
+
+
+def sbv_predict_draws_dev(mean_dev, var_dev, xi_dev, n_draws, stats_dev, stream=None):
+    """Draw summaries on the device: stats_dev gets (mean, var, lo, hi) x n_pred."""
+    n = int(mean_dev.numel()) if hasattr(mean_dev, "numel") else None
+    _check(lib().sbv_predict_draws_dev(C.c_void_p(_ptr(mean_dev)), C.c_void_p(_ptr(var_dev)), n,
+                                       C.c_void_p(_ptr(xi_dev)), int(n_draws), C.c_void_p(_ptr(stats_dev)),
+                                       C.c_void_p(_stream(stream))))

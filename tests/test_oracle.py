@@ -344,3 +344,59 @@ def test_block_parts_recombine_to_the_term():
     w = np.linalg.solve(L0, y[B0])
     assert abs(ud[0, 0] - w @ w) < 1e-10 * max(1.0, w @ w)
     assert abs(ud[0, 1] - 2 * np.sum(np.log(np.diag(L0)))) < 1e-10 * max(1.0, abs(ud[0, 1]))
+
+
+# --- Prediction: Sec. 5.5 with the block-conditional product of Sec. 4.2 --
+def _exact_conditional(X, y, Xp, th, two_nu):
+    """Dense GP conditional of new noisy observations given all observations
+    (the joint normal of the new and observed outputs, numpy solves)."""
+    K = O.cov_matrix(X, X, th, two_nu, True)
+    Kx = O.cov_matrix(Xp, X, th, two_nu, False)
+    Kp = O.cov_matrix(Xp, Xp, th, two_nu, True)
+    A = np.linalg.solve(K, Kx.T)
+    return Kx @ np.linalg.solve(K, y), np.diag(Kp - Kx @ A)
+
+
+def test_prediction_with_all_observations_is_the_exact_conditional():
+    X, y, th = _data(300, 3, 81, [0.3, 0.5, 0.8], t2=1e-2)
+    Xp = np.random.default_rng(82).random((45, 3))
+    P = O.pred_structure(X, Xp, np.exp(th[:3]), K=9, m=300, lloyd_iters=2, seed=4)
+    assert np.all(np.diff(P.nn_ptr) == 300)
+    mean, var = O.predict(X, y, Xp, P, th, 5)
+    em, ev = _exact_conditional(X, y, Xp, th, 5)
+    assert np.max(np.abs(mean - em)) < 1e-10 * max(1.0, np.max(np.abs(em)))
+    assert np.max(np.abs(var - ev) / ev) < 1e-9
+
+
+def test_prediction_neighbours_are_brute_force_and_variance_shrinks_with_m():
+    X, y, th = _data(400, 4, 83, [0.2, 0.4, 0.6, 1.0], t2=1e-3)
+    Xp = np.random.default_rng(84).random((60, 4))
+    bb = np.exp(th[:4])
+    Z, Zp = X / bb, Xp / bb
+    prev = None
+    for m in (5, 20, 60):
+        P = O.pred_structure(X, Xp, bb, K=12, m=m, lloyd_iters=3, seed=5)
+        for r in range(P.K):
+            Bp, J = P.block(r)
+            c = Zp[Bp].mean(0)
+            d2 = ((Z - c) ** 2).sum(1)
+            assert set(J.tolist()) == set(np.argsort(d2, kind="stable")[:m].tolist())
+        mean, var = O.predict(X, y, Xp, P, th, 5)
+        s2, t2 = np.exp(th[4]), np.exp(th[5])
+        assert np.all(var >= t2 * (1 - 1e-9)) and np.all(var <= (s2 + t2) * (1 + 1e-12))
+        if prev is not None:  # nested conditioning sets: the conditional variance cannot grow
+            assert np.all(var <= prev * (1 + 1e-10))
+        prev = var
+
+
+def test_prediction_draw_summaries_converge():
+    """Draw summaries: with 40,000 draws the sample mean and variance are within
+    a few standard errors of the mean and variance they were drawn from."""
+    rng = np.random.default_rng(85)
+    mean, var = rng.normal(size=50), rng.uniform(0.1, 2.0, 50)
+    N = 40000
+    xi = rng.standard_normal((N, 50))
+    m, v, lo, hi = O.pred_draws(mean, var, xi)
+    assert np.all(np.abs(m - mean) < 6 * np.sqrt(var / N))
+    assert np.all(np.abs(v - var) < 6 * var * np.sqrt(2.0 / N))
+    assert np.allclose(hi - lo, 2 * 1.959963984540054 * np.sqrt(v), rtol=1e-12)
