@@ -339,6 +339,18 @@ sbv_status sbv_autotune(const sbv_blocks* sets, int32_t n_sets, const int32_t* t
                         int32_t prec, int32_t reps, int32_t* chosen_tiles, int32_t* chosen_lookahead,
                         int32_t* chosen_waves);
 
+/*
+ * Dense covariance matrix of Eq. (maternkernel) between two point lists, on the
+ * device: out_dev[a * nb + b] = sigma^2 rho(r_ab) with r_ab the distance of
+ * Sec. 4.4 Eq. (scale), plus tau^2 when same != 0 and a == b (the two lists
+ * are the same observations).  Xa_dev (na x d), Xb_dev (nb x d), theta_dev
+ * (d + 2 log-parameters) and out_dev (na x nb, row-major) are device buffers;
+ * asynchronous on `stream`.  For exact-GP comparisons (Eq. (1), the KL
+ * divergence of Eq. (kldivergence)) and data generation at small n.
+ */
+sbv_status sbv_cov_matrix_dev(const double* Xa_dev, int64_t na, const double* Xb_dev, int64_t nb, int32_t d,
+                              const double* theta_dev, int32_t two_nu, int32_t same, double* out_dev, void* stream);
+
 /* Number of blocks recomputed in FP64 by the last SBV_FP32 evaluation of this
  * handle (synchronises the device). */
 sbv_status sbv_blocks_fallback_count(sbv_blocks h, int64_t* count);

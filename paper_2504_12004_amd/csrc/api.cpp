@@ -953,6 +953,16 @@ sbv_status sbv_plan_flops(const sbv_blocks* sets, int32_t n_sets, const int32_t*
   return SBV_OK;
 }
 
+sbv_status sbv_cov_matrix_dev(const double* Xa_dev, int64_t na, const double* Xb_dev, int64_t nb, int32_t d,
+                              const double* theta_dev, int32_t two_nu, int32_t same, double* out_dev, void* stream) {
+  if (!Xa_dev || !Xb_dev || !theta_dev || !out_dev || na <= 0 || nb <= 0 || d <= 0)
+    return fail(SBV_E_INVAL, "device buffers and positive sizes are required");
+  if (two_nu != 1 && two_nu != 3 && two_nu != 5 && two_nu != 7) return fail(SBV_E_INVAL, "two_nu must be 1, 3, 5 or 7");
+  if (same && na != nb) return fail(SBV_E_INVAL, "same = 1 needs na == nb");
+  HIP_TRY(launch_cov_matrix(Xa_dev, na, Xb_dev, nb, d, theta_dev, two_nu, same, out_dev, (hipStream_t)stream));
+  return SBV_OK;
+}
+
 sbv_status sbv_blocks_terms(sbv_blocks h, double* terms) {
   if (!h || !terms) return fail(SBV_E_INVAL, "handle and terms are required");
   HIP_TRY(hipDeviceSynchronize());

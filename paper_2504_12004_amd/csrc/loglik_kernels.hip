@@ -2201,6 +2201,35 @@ hipError_t launch_reduce_grad(const SetDesc* sets, int n_sets, double* out, cons
   return hipGetLastError();
 }
 
+// ---- dense covariance matrix (Eq. (maternkernel) between two point lists) --
+// out[a * nb + b] = sigma^2 rho(r_ab) (+ tau^2 when same and a == b), with the
+// coordinates scaled as in the block kernels (x * exp(-theta_k)).  One thread
+// per entry, rows of out contiguous.
+__global__ void k_cov_matrix(const double* __restrict__ Xa, int64_t na, const double* __restrict__ Xb, int64_t nb,
+                             int d, const double* __restrict__ theta, int two_nu, int same, double* __restrict__ out) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= na * nb) return;
+  const int64_t a = e / nb, b = e - a * nb;
+  double r2 = 0.0;
+  for (int k = 0; k < d; ++k) {
+    const double sc = exp(-theta[k]);
+    const double df = Xa[a * d + k] * sc - Xb[b * d + k] * sc;
+    r2 += df * df;
+  }
+  double v = exp(theta[d]) * matern<double>(g_sqrt(r2), two_nu);
+  if (same && a == b) v += exp(theta[d + 1]);
+  out[e] = v;
+}
+
+hipError_t launch_cov_matrix(const double* Xa, int64_t na, const double* Xb, int64_t nb, int d, const double* theta,
+                             int two_nu, int same, double* out, hipStream_t s) {
+  const int64_t n = na * nb;
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_cov_matrix, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, Xa, na, Xb, nb, d, theta,
+                     two_nu, same, out);
+  return hipGetLastError();
+}
+
 // ---- FP32 fallback list: items whose fp32 pivot test fired ----------------
 __global__ void k_flag_compact(const SetDesc* __restrict__ sets, const WorkItem* __restrict__ items,
                                const int* __restrict__ count, WorkItem* __restrict__ out,

@@ -144,6 +144,11 @@ struct HandleView {
   int64_t n;
 };
 
+// Dense covariance matrix between two point lists (device buffers; theta on
+// the device, d + 2 log-parameters).
+hipError_t launch_cov_matrix(const double* Xa, int64_t na, const double* Xb, int64_t nb, int d, const double* theta,
+                             int two_nu, int same, double* out, hipStream_t s);
+
 // Pivot threshold of the FP32 path (a block whose FP32 pivot falls to or
 // below this fraction of its original diagonal is recomputed in FP64).
 double fp32_pivot_tau();

@@ -3,6 +3,7 @@
     python -m paper_2504_12004_amd.experiments c3 --out results/c3.json
     python -m paper_2504_12004_amd.experiments c4 --out results/c4.json
     python -m paper_2504_12004_amd.experiments c5 --out results/c5.json
+    python -m paper_2504_12004_amd.experiments accuracy --out results/accuracy.json
 
 c4: n = 5e6, d = 10, Matern-5/2, 250,000 k-means blocks of 5..60 points,
 m = 400 (joint sets up to 460, the large path).  Observations from the
@@ -320,7 +321,7 @@ def c3(out_path, reps=3):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("what", choices=["c3", "c4", "c5"])
+    ap.add_argument("what", choices=["c3", "c4", "c5", "accuracy"])
     ap.add_argument("--out", required=True)
     ap.add_argument("--reps", type=int, default=3)
     ap.add_argument("--no-fits", action="store_true")
@@ -334,6 +335,9 @@ def main():
         c3(a.out, a.reps)
     elif a.what == "c5":
         c5(a.out, n_train=a.train_sets, n_app=a.app_n)
+    elif a.what == "accuracy":
+        from . import accuracy
+        accuracy.study(a.out)
 
 
 if __name__ == "__main__":

@@ -105,6 +105,8 @@ def lib():
         "sbv_predict": (C.c_int, [_h, _d, C.c_int32, _d, _d]),
         "sbv_predict_draws_dev": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int32, C.c_void_p,
                                             C.c_void_p]),
+        "sbv_cov_matrix_dev": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_int32, C.c_void_p,
+                                         C.c_int32, C.c_int32, C.c_void_p, C.c_void_p]),
         "sbv_eval_graph_dev": (C.c_int, [C.POINTER(_h), C.c_int32, C.c_void_p, _i32, C.c_int32, C.c_int32,
                                          C.c_void_p, C.c_void_p, C.c_void_p]),
         "sbv_autotune": (C.c_int, [C.POINTER(_h), C.c_int32, _i32, _d, C.c_int32, C.c_int32, _i32, _i32, _i32]),
@@ -583,3 +585,12 @@ def sbv_predict_draws_dev(mean_dev, var_dev, xi_dev, n_draws, stats_dev, stream=
     _check(lib().sbv_predict_draws_dev(C.c_void_p(_ptr(mean_dev)), C.c_void_p(_ptr(var_dev)), n,
                                        C.c_void_p(_ptr(xi_dev)), int(n_draws), C.c_void_p(_ptr(stats_dev)),
                                        C.c_void_p(_stream(stream))))
+
+
+def sbv_cov_matrix_dev(Xa_dev, Xb_dev, theta_dev, two_nu, out_dev, same=False, stream=None):
+    """Dense covariance matrix on the device (torch tensors: Xa na x d, Xb nb x d, out na x nb)."""
+    na, d = Xa_dev.shape
+    nb = Xb_dev.shape[0]
+    _check(lib().sbv_cov_matrix_dev(C.c_void_p(_ptr(Xa_dev)), int(na), C.c_void_p(_ptr(Xb_dev)), int(nb), int(d),
+                                    C.c_void_p(_ptr(theta_dev)), int(two_nu), int(bool(same)),
+                                    C.c_void_p(_ptr(out_dev)), C.c_void_p(_stream(stream))))
