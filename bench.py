@@ -97,11 +97,12 @@ def main():
     log(f"simulated observations in {time.perf_counter() - t0:.2f}s")
 
     # per size bucket, pick the fastest kernel variant and schedule (setup, not timed)
-    tuned, sched = {}, {}
+    tuned, sched, pers_choice = {}, {}, {}
     for name, prec in (("fp64", sbv.SBV_FP64), ("fp32", sbv.SBV_FP32)):
-        ch, la, wv = sbv.sbv_autotune([B], theta_true, two_nu, prec, reps=3, with_schedule=True)
+        ch, la, wv, pc = sbv.sbv_autotune([B], theta_true, two_nu, prec, reps=3, with_schedule=True)
         tuned[name] = [int(t) for t in ch]
         sched[name] = [("lookahead" if x else "plain") + f"/{int(v)}w" for x, v in zip(la, wv)]
+        pers_choice[name] = "persistent single launch" if pc else "one launch per size bucket"
     log(f"autotuned tiles per bucket: {tuned}, schedules {sched}")
 
     thetas = synth.perturbed_thetas(theta_true, w["n_theta"], w["theta_seed"])
@@ -162,6 +163,23 @@ def main():
         grad_rate[name] = 1000.0 * kin / e0.elapsed_time(e1)
     log(f"loglik + gradient: {grad_rate['fp64']:.2f} evals/s FP64, {grad_rate['fp32']:.2f} evals/s FP32")
 
+    # both launch modes timed explicitly (the autotuner's choice is used above):
+    # one launch per size bucket, and one persistent launch for all buckets
+    persistent = {"autotuner_choice": pers_choice}
+    for mode in ("0", "1"):
+        os.environ["SBV_PERSISTENT"] = mode
+        try:
+            for name, prec in (("fp64", sbv.SBV_FP64), ("fp32", sbv.SBV_FP32)):
+                msp, _, llp = run(prec, kin, 2, False)
+                ref = ll64[:kin] if prec == sbv.SBV_FP64 else ll32[:kin]
+                key = "persistent" if mode == "1" else "per_bucket"
+                persistent[f"{name}_{key}"] = {
+                    "ms_per_eval": msp / kin,
+                    "max_rel_diff_vs_timed": float(np.max(np.abs(llp[:kin] - ref) / np.abs(ref)))}
+        finally:
+            del os.environ["SBV_PERSISTENT"]
+    log(f"launch modes: {persistent}")
+
     small = small_leg(sbv, torch, dev, stream)
 
     fits = None
@@ -203,6 +221,7 @@ def main():
             "grad_fp64_evals_per_s": grad_rate["fp64"],
             "grad_fp32_evals_per_s": grad_rate["fp32"],
             "small_20k": {k: v for k, v in small.items() if not k.startswith("_")},
+            "persistent_single_launch": persistent,
             "build_seconds": t_build,
             "autotuned_tiles": tuned,
             "autotuned_schedules": sched,
@@ -315,6 +334,21 @@ def large_leg(sbv, torch, dev, stream, steps):
         log(f"m400_5m {name}: {ms:.1f} ms/eval, large bucket {large_ms:.1f} ms, "
             f"{res[name]['total_algorithmic_tflops']:.2f} TFLOP/s algorithmic")
     res["fp32_rel_diff_vs_fp64"] = abs(vals["fp32"] - vals["fp64"]) / abs(vals["fp64"])
+    # log-likelihood + gradient (large-path adjoint), FP64 and FP32
+    g = torch.empty(len(theta), dtype=torch.float64, device=dev)
+    for name, prec in (("fp64", sbv.SBV_FP64), ("fp32", sbv.SBV_FP32)):
+        sbv.sbv_loglik_grad_dev(B, th_d, two_nu, out[0:1], g, prec, stream)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for i in range(steps):
+            sbv.sbv_loglik_grad_dev(B, th_d, two_nu, out[1 + i:2 + i], g, prec, stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        res[name]["grad_evals_per_s"] = 1000.0 / ms
+        res[name]["grad_ms_per_eval"] = ms
+        log(f"m400_5m {name} loglik+grad: {ms:.1f} ms/eval")
     B.free()
     return res
 

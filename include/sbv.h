@@ -58,15 +58,20 @@ typedef struct {
   int32_t lloyd_iters; /* k-means passes after the anchor assignment (ignored for RAC)   */
   int32_t min_bs;      /* smallest block size (0: no bound)                              */
   int32_t max_bs;      /* largest block size (0: no bound)                               */
-  int32_t reserved;    /* must be 0                                                      */
+  int32_t n_slabs;     /* Alg. 2 slabs along the most relevant scaled dimension (0, 1:   */
+                       /* one slab); blocks are clustered within their slab             */
   uint64_t seed;       /* anchors use seed, the block order seed + 1                     */
+  double nns_alpha;    /* neighbour search: > 0 filtered with this expansion factor     */
+                       /* (Eq. (distancethreashold)), < 0 brute force, 0 automatic      */
 } sbv_build_opts;
 
 /*
  * Build the block structure on the device (Alg. 2 scaling by beta_build, Alg. 3
  * anchors + optional k-means, random block order of Alg. 1, block centroids and
- * the exact m nearest points of strictly earlier blocks of Alg. 4 -- brute force,
- * no distance threshold).  X: host, row-major n x d FP64; y: host, n FP64 (may be
+ * the exact m nearest points of strictly earlier blocks of Alg. 4: a filtered
+ * search whose distance threshold follows Eq. (distancethreashold) with a
+ * conservative candidate test and a retry at twice the threshold until the
+ * answer is provably exact, or brute force; both give the same sets).  X: host, row-major n x d FP64; y: host, n FP64 (may be
  * NULL: observations set to 0).  n_blocks: requested block count K (<= n); the
  * final count can differ when size bounds split or merge clusters.  m >= 0.
  * On success *out owns device copies of X and y in block order.
@@ -333,11 +338,16 @@ sbv_status sbv_eval_graph_dev(const sbv_blocks* sets, int32_t n_sets, const doub
  * where the lookahead schedule won, else 0 (always 0 for the large-block
  * bucket, which has a single schedule); chosen_waves (optional, 16 entries)
  * the waves per workgroup of the chosen kernel (16-wave kernels exist for
- * FP32 only).  Synchronous.
+ * FP32 only).  Then whole evaluations with one launch per size bucket are
+ * timed against ONE persistent launch for all register-path blocks of all
+ * sets (the largest chosen variant, workgroups taking blocks longest first
+ * from a device counter); chosen_persistent (optional) receives 1 when the
+ * persistent launch won.  The environment variable SBV_PERSISTENT=1 / =0
+ * overrides that choice at evaluation time.  Synchronous.
  */
 sbv_status sbv_autotune(const sbv_blocks* sets, int32_t n_sets, const int32_t* two_nu, const double* theta,
                         int32_t prec, int32_t reps, int32_t* chosen_tiles, int32_t* chosen_lookahead,
-                        int32_t* chosen_waves);
+                        int32_t* chosen_waves, int32_t* chosen_persistent);
 
 /*
  * Dense covariance matrix of Eq. (maternkernel) between two point lists, on the

@@ -171,6 +171,13 @@ struct Plan {
   std::vector<Bucket> buckets;
   DevBuf<double> theta, out;
   DevBuf<int> bad;
+  // persistent mode: every register-path item of every set in one list
+  // (buckets concatenated, longest first), served by one launch whose
+  // workgroups pull items from a device counter
+  int all_n = 0;
+  int persist[2] = {0, 0};  // per precision: 1 when the autotuner chose the persistent launch
+  DevBuf<WorkItem> all_items, all_fb_items;
+  DevBuf<int> all_count, all_fb_count, queue;
 };
 
 namespace {
@@ -284,6 +291,21 @@ sbv_status get_plan(const sbv_blocks* sets, int32_t n_sets, const int32_t* two_n
     B.la[0] = B.la[1] = la && la[0] == '1';
     P->buckets.push_back(std::move(B));
   }
+  {
+    std::vector<WorkItem> all;
+    for (int v = n_variants() - 1; v >= 0; --v)
+      for (const auto& e : per[v]) all.push_back(e.second);  // per[v] is sorted longest first above
+    P->all_n = (int)all.size();
+    if (P->all_n > 0) {
+      HIP_TRY(P->all_items.alloc(all.size()));
+      HIP_TRY(hipMemcpy(P->all_items.p, all.data(), sizeof(WorkItem) * all.size(), hipMemcpyHostToDevice));
+      HIP_TRY(P->all_count.alloc(1));
+      HIP_TRY(hipMemcpy(P->all_count.p, &P->all_n, sizeof(int), hipMemcpyHostToDevice));
+      HIP_TRY(P->all_fb_items.alloc(all.size()));
+      HIP_TRY(P->all_fb_count.alloc(1));
+      HIP_TRY(P->queue.alloc(1));
+    }
+  }
   *out = P.get();
   g_plans.push_back(std::move(P));
   return SBV_OK;
@@ -370,10 +392,62 @@ sbv_status run_plan_grad(Plan* P, int32_t prec, hipStream_t s) {
   return SBV_OK;
 }
 
+// Persistent mode: the register-path blocks of all sets go through ONE launch
+// of the largest kernel variant any bucket uses, longest first, each
+// workgroup taking its next block from a device counter; the FP32 fallback
+// pass is one such launch too.  The large-set bucket keeps its own launches.
+// The autotuner chooses it per plan and precision; the environment variable
+// SBV_PERSISTENT (read at every queued evaluation) forces it on (1) or off (0).
+bool persistent_mode(const Plan* P, int pk, int force) {
+  if (force >= 0) return force == 1;
+  const char* e = std::getenv("SBV_PERSISTENT");
+  if (e && (e[0] == '0' || e[0] == '1')) return e[0] == '1';
+  return P->persist[pk] == 1;
+}
+
+sbv_status run_persistent(Plan* P, int pk, hipStream_t s) {
+  int v = -1, la = 0;
+  for (const auto& B : P->buckets)
+    if (!B.large && B.use(pk) > v) {
+      v = B.use(pk);
+      la = B.la[pk];
+    }
+  if (v < 0) return SBV_OK;
+  const int grid = std::min(P->all_n, 1024);
+  TimedLaunch tl{pk, v, nullptr, nullptr};
+  if (g_timing) {
+    HIP_TRY(hipEventCreate(&tl.a));
+    HIP_TRY(hipEventCreate(&tl.b));
+    HIP_TRY(hipEventRecord(tl.a, s));
+  }
+  HIP_TRY(launch_zero_int(P->queue.p, 1, s));
+  HIP_TRY(launch_loglik(pk, v, grid, P->dsets.p, P->theta.p, P->all_items.p, P->all_count.p,
+                        pk ? g_piv_tau : 0.0, s, false, la != 0, P->queue.p));
+  if (g_timing) {
+    HIP_TRY(hipEventRecord(tl.b, s));
+    g_timed.push_back(tl);
+  }
+  if (pk) {
+    HIP_TRY(launch_zero_int(P->all_fb_count.p, 1, s));
+    HIP_TRY(launch_flag_compact(P->dsets.p, P->all_items.p, P->all_count.p, P->all_fb_items.p, P->all_fb_count.p, s));
+    HIP_TRY(launch_zero_int(P->queue.p, 1, s));
+    HIP_TRY(launch_loglik(0, v, grid, P->dsets.p, P->theta.p, P->all_fb_items.p, P->all_fb_count.p, 0.0, s,
+                          false, false, P->queue.p));
+  }
+  return SBV_OK;
+}
+
 // Queue one evaluation of plan P (theta already in P->theta) on stream s;
-// result in P->out.
-sbv_status run_plan(Plan* P, int32_t prec, hipStream_t s) {
+// result in P->out.  force_persistent: -1 follows the plan's choice (and the
+// environment), 0 / 1 forces per-bucket launches / the persistent launch.
+sbv_status run_plan(Plan* P, int32_t prec, hipStream_t s, int force_persistent = -1) {
+  const bool pers = persistent_mode(P, prec == SBV_FP32 ? 1 : 0, force_persistent) && P->all_n > 0;
+  if (pers) {
+    sbv_status st = run_persistent(P, prec == SBV_FP32 ? 1 : 0, s);
+    if (st) return st;
+  }
   for (auto& B : P->buckets) {
+    if (pers && !B.large) continue;
     TimedLaunch tl{prec == SBV_FP32 ? 1 : 0, B.variant, nullptr, nullptr};  // keyed by size bucket
     if (g_timing) {
       HIP_TRY(hipEventCreate(&tl.a));
@@ -765,7 +839,7 @@ sbv_status sbv_sample(sbv_blocks h, const double* theta, int32_t two_nu, const d
 // bucket's largest joint size and keep the fastest.
 sbv_status sbv_autotune(const sbv_blocks* sets, int32_t n_sets, const int32_t* two_nu, const double* theta,
                         int32_t prec, int32_t reps, int32_t* chosen_tiles, int32_t* chosen_lookahead,
-                        int32_t* chosen_waves) {
+                        int32_t* chosen_waves, int32_t* chosen_persistent) {
   sbv_status st = check_sets(sets, n_sets, two_nu);
   if (st) return st;
   if (!theta || reps <= 0) return fail(SBV_E_INVAL, "theta and reps > 0 are required");
@@ -817,6 +891,30 @@ sbv_status sbv_autotune(const sbv_blocks* sets, int32_t n_sets, const int32_t* t
     if (chosen_waves) chosen_waves[bi] = (pk == 0 && variant(bestv).nw > 8) ? 8 : variant(bestv).nw;
     ++bi;
   }
+  // whole evaluations: per-bucket launches against the persistent launch
+  if (P->all_n > 0) {
+    float best_t = INFINITY;
+    int best_p = 0;
+    for (int pm = 0; pm < 2; ++pm) {
+      sbv_status rs = run_plan(P, prec, nullptr, pm);
+      if (rs) return rs;
+      HIP_TRY(hipEventRecord(a, nullptr));
+      for (int r = 0; r < reps; ++r) {
+        rs = run_plan(P, prec, nullptr, pm);
+        if (rs) return rs;
+      }
+      HIP_TRY(hipEventRecord(b, nullptr));
+      HIP_TRY(hipEventSynchronize(b));
+      float ms = 0.f;
+      HIP_TRY(hipEventElapsedTime(&ms, a, b));
+      if (ms < best_t) {
+        best_t = ms;
+        best_p = pm;
+      }
+    }
+    P->persist[pk] = best_p;
+  }
+  if (chosen_persistent) *chosen_persistent = P->persist[pk];
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(b);
   // captured graphs may hold the old choice

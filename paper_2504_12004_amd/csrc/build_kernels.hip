@@ -113,15 +113,18 @@ __global__ __launch_bounds__(kKnnWaves * 64) void k_knn(const double* __restrict
                                                         const double* __restrict__ cen,
                                                         const int32_t* __restrict__ bptr, int K, int m,
                                                         const int64_t* __restrict__ nn_ptr,
-                                                        int32_t* __restrict__ nn_pos) {
+                                                        int32_t* __restrict__ nn_pos,
+                                                        const int32_t* __restrict__ qlist, int nq) {
   __shared__ KnnSmem sm;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // queries: blocks 0..K-1, or the ranks listed in qlist (ascending)
+  const int nqq = qlist ? nq : K;
   const int q0 = blockIdx.x * kKnnWaves;
-  const int q = q0 + wave;
-  const bool active = q < K;
+  const bool active = q0 + wave < nqq;
+  const int q = active ? (qlist ? qlist[q0 + wave] : q0 + wave) : 0;
   const int prefix = active ? bptr[q] : 0;  // points of strictly earlier blocks
-  const int qlast = min(q0 + kKnnWaves, K) - 1;
-  const int maxprefix = bptr[qlast];
+  const int ilast = min(q0 + kKnnWaves, nqq) - 1;
+  const int maxprefix = bptr[qlist ? qlist[ilast] : ilast];
   double c[kMaxDim];
 #pragma unroll
   for (int k = 0; k < kMaxDim; ++k) c[k] = (active && k < d) ? cen[(int64_t)q * d + k] : 0.0;
@@ -172,10 +175,150 @@ __global__ __launch_bounds__(kKnnWaves * 64) void k_knn(const double* __restrict
 }
 
 hipError_t launch_knn(const double* Z, int d, const double* cen, const int32_t* bptr, int K, int m,
-                      const int64_t* nn_ptr, int32_t* nn_pos, hipStream_t s) {
-  if (K <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_knn, dim3((K + kKnnWaves - 1) / kKnnWaves), dim3(kKnnWaves * 64), 0, s, Z, d, cen,
-                     bptr, K, m, nn_ptr, nn_pos);
+                      const int64_t* nn_ptr, int32_t* nn_pos, hipStream_t s, const int32_t* qlist, int nq) {
+  const int nqq = qlist ? nq : K;
+  if (nqq <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_knn, dim3((nqq + kKnnWaves - 1) / kKnnWaves), dim3(kKnnWaves * 64), 0, s, Z, d, cen,
+                     bptr, K, m, nn_ptr, nn_pos, qlist, nq);
+  return hipGetLastError();
+}
+
+// ---- filtered neighbour search (Alg. 4 with Eq. (distancethreashold)) -----
+// Coarse step: for each query block q (one thread each, the ranks of a
+// workgroup ascending), every earlier block j whose centroid lies within
+// lambda_q + radius_j of q's centroid is a candidate: any point of j within
+// lambda_q of c_q forces ||c_q - c_j|| <= lambda_q + radius_j.  Centroid
+// tiles are shared through LDS.  cand holds at most cap ids per query; the
+// count keeps running past cap so that an overflow is visible.
+constexpr int kCoarseTile = 256;
+
+__global__ __launch_bounds__(256) void k_knn_coarse(const double* __restrict__ cen, const double* __restrict__ rad,
+                                                    int d, const int32_t* __restrict__ qlist, int nq,
+                                                    const double* __restrict__ lam, int cap,
+                                                    int32_t* __restrict__ cand, int32_t* __restrict__ ccount) {
+  __shared__ double cs[kCoarseTile * kMaxDim];
+  __shared__ double rs[kCoarseTile];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool active = i < nq;
+  const int q = active ? qlist[i] : 0;
+  const int qmax = qlist[min((int)(blockIdx.x * blockDim.x + blockDim.x), nq) - 1];
+  double c[kMaxDim];
+#pragma unroll
+  for (int k = 0; k < kMaxDim; ++k) c[k] = (active && k < d) ? cen[(int64_t)q * d + k] : 0.0;
+  const double lq = active ? lam[i] : 0.0;
+  int cnt = 0;
+  for (int j0 = 0; j0 < qmax; j0 += kCoarseTile) {
+    const int jn = min(kCoarseTile, qmax - j0);
+    __syncthreads();
+    for (int e = threadIdx.x; e < jn * d; e += blockDim.x) cs[e] = cen[(int64_t)j0 * d + e];
+    for (int e = threadIdx.x; e < jn; e += blockDim.x) rs[e] = rad[j0 + e];
+    __syncthreads();
+    const int lim = active ? min(jn, q - j0) : 0;
+    for (int t = 0; t < lim; ++t) {
+      double s2 = 0.0;
+#pragma unroll
+      for (int k = 0; k < kMaxDim; ++k)
+        if (k < d) {
+          const double df = c[k] - cs[t * d + k];
+          s2 += df * df;
+        }
+      const double thr = (lq + rs[t]) * (1.0 + 1e-12);
+      if (s2 <= thr * thr) {
+        if (cnt < cap) cand[(int64_t)i * cap + cnt] = j0 + t;
+        ++cnt;
+      }
+    }
+  }
+  if (active) ccount[i] = cnt;
+}
+
+// Fine step: one wave per query; the points of its candidate blocks within
+// lambda_q of the centroid go through the same candidate buffer and sort as the
+// brute-force search.  The result is exact when at least m_q points lie within
+// lambda_q (every point that close was examined); otherwise, or when the
+// candidate list overflowed, status[i] = 1 and the query is retried.
+__global__ __launch_bounds__(kKnnWaves * 64) void k_knn_fine(const double* __restrict__ Z, int d,
+                                                             const double* __restrict__ cen,
+                                                             const int32_t* __restrict__ bptr,
+                                                             const int32_t* __restrict__ qlist, int nq,
+                                                             const double* __restrict__ lam, int cap,
+                                                             const int32_t* __restrict__ cand,
+                                                             const int32_t* __restrict__ ccount,
+                                                             const int64_t* __restrict__ nn_ptr,
+                                                             int32_t* __restrict__ nn_pos, int32_t* __restrict__ status) {
+  __shared__ KnnSmem sm;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int i = blockIdx.x * kKnnWaves + wave;
+  if (i >= nq) return;  // whole wave; no workgroup barrier below
+  const int q = qlist[i];
+  const int mi = (int)(nn_ptr[q + 1] - nn_ptr[q]);
+  const int nc = ccount[i];
+  if (nc > cap) {
+    if (lane == 0) status[i] = 1;
+    return;
+  }
+  double c[kMaxDim];
+#pragma unroll
+  for (int k = 0; k < kMaxDim; ++k) c[k] = k < d ? cen[(int64_t)q * d + k] : 0.0;
+  const double l2 = lam[i] * lam[i];
+  double* bd = sm.bd[wave];
+  int32_t* bpos = sm.bp[wave];
+  int cnt = 0, inside = 0;
+  double tau = l2;
+  for (int u = 0; u < nc; ++u) {
+    const int j = cand[(int64_t)i * cap + u];
+    const int p0 = bptr[j], p1 = bptr[j + 1];
+    for (int pb = p0; pb < p1; pb += 64) {
+      if (cnt > kKnnCap - 64) {
+        knn_sort(bd, bpos, cnt, lane);
+        cnt = min(cnt, mi);
+        tau = (cnt >= mi) ? bd[mi - 1] : l2;
+      }
+      const int p = pb + lane;
+      double s2 = __builtin_inf();
+      if (p < p1) {
+        s2 = 0.0;
+#pragma unroll
+        for (int k = 0; k < kMaxDim; ++k)
+          if (k < d) {
+            const double df = Z[(int64_t)p * d + k] - c[k];
+            s2 += df * df;
+          }
+      }
+      inside += __popcll(__ballot(p < p1 && s2 <= l2));
+      const bool keep = p < p1 && s2 <= tau;
+      const unsigned long long mask = __ballot(keep);
+      if (keep) {
+        const int off = __popcll(mask & ((1ull << lane) - 1ull));
+        bd[cnt + off] = s2;
+        bpos[cnt + off] = p;
+      }
+      cnt += __popcll(mask);
+    }
+  }
+  if (inside < mi) {
+    if (lane == 0) status[i] = 1;
+    return;
+  }
+  knn_sort(bd, bpos, cnt, lane);
+  for (int e = lane; e < mi; e += 64) nn_pos[nn_ptr[q] + e] = bpos[e];
+  if (lane == 0) status[i] = 0;
+}
+
+hipError_t launch_knn_coarse(const double* cen, const double* rad, int d, const int32_t* qlist, int nq,
+                             const double* lam, int cap, int32_t* cand, int32_t* ccount, hipStream_t s) {
+  if (nq <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_knn_coarse, dim3((nq + 255) / 256), dim3(256), 0, s, cen, rad, d, qlist, nq, lam, cap, cand,
+                     ccount);
+  return hipGetLastError();
+}
+
+hipError_t launch_knn_fine(const double* Z, int d, const double* cen, const int32_t* bptr, const int32_t* qlist,
+                           int nq, const double* lam, int cap, const int32_t* cand, const int32_t* ccount,
+                           const int64_t* nn_ptr, int32_t* nn_pos, int32_t* status, hipStream_t s) {
+  if (nq <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_knn_fine, dim3((nq + kKnnWaves - 1) / kKnnWaves), dim3(kKnnWaves * 64), 0, s, Z, d, cen,
+                     bptr, qlist, nq, lam, cap, cand, ccount, nn_ptr, nn_pos, status);
   return hipGetLastError();
 }
 

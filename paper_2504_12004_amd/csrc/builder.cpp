@@ -29,9 +29,7 @@
 namespace sbv {
 hipError_t launch_assign(const double* Z, int64_t n, int d, const double* C, int K, int32_t* lab,
                          double* best_d2, hipStream_t s);
-hipError_t launch_knn(const double* Z, int d, const double* cen, const int32_t* bptr, int K, int m,
-                      const int64_t* nn_ptr, int32_t* nn_pos, hipStream_t s);
-int knn_max_m();
+
 }  // namespace sbv
 
 sbv_status sbv_internal_fail(sbv_status st, const char* msg);
@@ -100,33 +98,13 @@ void cluster_means(const std::vector<double>& Z, int64_t n, int d, const std::ve
       for (int k = 0; k < d; ++k) C[c * d + k] /= (double)cnt[c];
 }
 
-}  // namespace
-
-extern "C" sbv_status sbv_build_blocks(const double* X, const double* y, int64_t n, int32_t d,
-                                       const double* beta_build, int64_t n_blocks, int32_t m,
-                                       const sbv_build_opts* opts, sbv_blocks* out) {
-  if (!X || !beta_build || !out) return sbv_internal_fail(SBV_E_INVAL, "X, beta_build and out are required");
-  if (n <= 0 || d <= 0 || d > kMaxDim || n_blocks <= 0 || n_blocks > n || m < 0)
-    return sbv_internal_fail(SBV_E_INVAL, "need n > 0, 0 < d <= 20, 0 < n_blocks <= n, m >= 0");
-  if (n > INT32_MAX - 1 || n_blocks > INT32_MAX / 2) return sbv_internal_fail(SBV_E_INVAL, "n too large");
-  if (m > knn_max_m()) return sbv_internal_fail(SBV_E_INVAL, "m exceeds the neighbour-search capacity");
-  sbv_build_opts o{SBV_KMEANS, 10, 0, 0, 0, 0};
-  if (opts) o = *opts;
-  if (o.method != SBV_KMEANS && o.method != SBV_RAC) return sbv_internal_fail(SBV_E_INVAL, "unknown method");
-  if (o.min_bs < 0 || o.max_bs < 0 || (o.max_bs > 0 && o.min_bs > o.max_bs))
-    return sbv_internal_fail(SBV_E_INVAL, "bad size bounds");
-  for (int k = 0; k < d; ++k)
-    if (!(beta_build[k] > 0.0) || !std::isfinite(beta_build[k]))
-      return sbv_internal_fail(SBV_E_INVAL, "beta_build must be positive and finite");
-  for (int64_t i = 0; i < n * d; ++i)
-    if (!std::isfinite(X[i])) return sbv_internal_fail(SBV_E_INVAL, "X has non-finite values");
-  const int lloyd = o.method == SBV_RAC ? 0 : std::max(0, o.lloyd_iters);
-  int64_t K = n_blocks;
-
-  // 1. scaling
-  std::vector<double> Z((size_t)n * d);
-  for (int64_t i = 0; i < n; ++i)
-    for (int k = 0; k < d; ++k) Z[i * d + k] = X[i * d + k] / beta_build[k];
+// Alg. 3 on one point set: K random anchors (partial Fisher-Yates with
+// SplitMix64(seed)), nearest-anchor assignment on the device, Lloyd passes
+// (empty clusters re-seeded with the point farthest from its centre), the
+// size bounds, and empty clusters dropped; lab receives cluster ids 0..K-1
+// and K the final count.
+sbv_status cluster_points(const std::vector<double>& Z, int64_t n, int d, int64_t& K, const sbv_build_opts& o,
+                          uint64_t seed, int lloyd, std::vector<int32_t>& lab) {
   Dev<double> dZ, dC;
   Dev<int32_t> dlab;
   Dev<double> dbest;
@@ -140,7 +118,7 @@ extern "C" sbv_status sbv_build_blocks(const double* X, const double* y, int64_t
   {
     std::vector<int64_t> perm(n);
     std::iota(perm.begin(), perm.end(), 0);
-    Splitmix rs{o.seed};
+    Splitmix rs{seed};
     for (int64_t i = 0; i < K; ++i) {
       int64_t j = i + (int64_t)rs.below((uint64_t)(n - i));
       std::swap(perm[i], perm[j]);
@@ -148,7 +126,8 @@ extern "C" sbv_status sbv_build_blocks(const double* X, const double* y, int64_t
     }
   }
   // 3.-4. assignment and Lloyd passes
-  std::vector<int32_t> lab(n), prev(n);
+  lab.assign(n, 0);
+  std::vector<int32_t> prev(n);
   std::vector<double> best(n);
   std::vector<int64_t> cnt;
   BTRY(dC.alloc((size_t)K * d));
@@ -265,6 +244,162 @@ extern "C" sbv_status sbv_build_blocks(const double* X, const double* y, int64_t
     for (int64_t i = 0; i < n; ++i) lab[i] = (int32_t)remap[lab[i]];
     K = Kf;
   }
+  return SBV_OK;
+}
+
+// Filtered exact neighbour search (Alg. 4 with the distance threshold of
+// Eq. (distancethreashold)).  Query block q (rank q, m_q neighbours among
+// the n_q points of earlier blocks) starts from the radius lambda_q of a ball
+// expected to hold alpha m_q of them:
+//   lambda_q = (alpha m_q zeta_d V / n_q)^(1/d),  zeta_d = Gamma(d/2 + 1) / pi^(d/2),
+// V the volume of the scaled inputs' bounding box.  Candidate blocks pass
+// ||c_q - c_j|| <= lambda_q + radius_j, candidate points ||z - c_q|| <= lambda_q,
+// and the answer is exact once at least m_q points lie within lambda_q.
+// Queries that fall short (or overflow their candidate list) retry with
+// 2 lambda_q, four times at most; what remains, and queries with fewer than
+// 8 m_q earlier points, go to the brute-force search.
+sbv_status filtered_knn(const std::vector<double>& Zo, const std::vector<double>& cen, const std::vector<int32_t>& bp,
+                        const std::vector<int64_t>& nptr, int64_t n, int d, int64_t K, double alpha, const double* dZo,
+                        const double* dcen, const int32_t* dbp, const int64_t* dnp, int32_t* dpos) {
+  // block radii and the bounding-box volume of the scaled inputs
+  std::vector<double> rad(K, 0.0), lo(d, INFINITY), hi(d, -INFINITY);
+  for (int64_t r = 0; r < K; ++r)
+    for (int64_t t = bp[r]; t < bp[r + 1]; ++t) {
+      double s2 = 0.0;
+      for (int k = 0; k < d; ++k) {
+        const double z = Zo[(size_t)t * d + k];
+        const double df = z - cen[(size_t)r * d + k];
+        s2 += df * df;
+        lo[k] = std::min(lo[k], z);
+        hi[k] = std::max(hi[k], z);
+      }
+      rad[r] = std::max(rad[r], std::sqrt(s2));
+    }
+  double logV = 0.0;
+  for (int k = 0; k < d; ++k) logV += std::log(std::max(hi[k] - lo[k], 1e-300));
+  const double log_zeta = std::lgamma(0.5 * d + 1.0) - 0.5 * d * std::log(M_PI);
+  std::vector<int32_t> pending, brute;
+  std::vector<double> lam(K, 0.0);
+  for (int64_t q = 0; q < K; ++q) {
+    const int64_t mq = nptr[q + 1] - nptr[q];
+    if (mq == 0) continue;
+    if (bp[q] < 8 * mq) {
+      brute.push_back((int32_t)q);
+      continue;
+    }
+    lam[q] = std::exp((std::log(alpha * (double)mq) + log_zeta + logV - std::log((double)bp[q])) / d);
+    pending.push_back((int32_t)q);
+  }
+  constexpr int kCap = 16384;     // candidate blocks per query
+  constexpr int kBatch = 8192;    // queries per pass
+  Dev<double> drad, dlam;
+  Dev<int32_t> dq, dcand, dcnt, dst;
+  BTRY(drad.alloc(K));
+  BTRY(hipMemcpy(drad.p, rad.data(), sizeof(double) * K, hipMemcpyHostToDevice));
+  BTRY(dlam.alloc(kBatch));
+  BTRY(dq.alloc(std::max<int64_t>(K, 1)));
+  BTRY(dcand.alloc((size_t)kBatch * kCap));
+  BTRY(dcnt.alloc(kBatch));
+  BTRY(dst.alloc(kBatch));
+  for (int attempt = 0; attempt < 5 && !pending.empty(); ++attempt) {
+    std::vector<int32_t> failed;
+    for (size_t b0 = 0; b0 < pending.size(); b0 += kBatch) {
+      const int nb = (int)std::min<size_t>(kBatch, pending.size() - b0);
+      std::vector<double> lb(nb);
+      for (int i = 0; i < nb; ++i) lb[i] = lam[pending[b0 + i]];
+      BTRY(hipMemcpy(dq.p, pending.data() + b0, sizeof(int32_t) * nb, hipMemcpyHostToDevice));
+      BTRY(hipMemcpy(dlam.p, lb.data(), sizeof(double) * nb, hipMemcpyHostToDevice));
+      BTRY(launch_knn_coarse(dcen, drad.p, d, dq.p, nb, dlam.p, kCap, dcand.p, dcnt.p, nullptr));
+      BTRY(launch_knn_fine(dZo, d, dcen, dbp, dq.p, nb, dlam.p, kCap, dcand.p, dcnt.p, dnp, dpos, dst.p, nullptr));
+      std::vector<int32_t> sb(nb);
+      BTRY(hipMemcpy(sb.data(), dst.p, sizeof(int32_t) * nb, hipMemcpyDeviceToHost));
+      for (int i = 0; i < nb; ++i)
+        if (sb[i]) failed.push_back(pending[b0 + i]);
+    }
+    for (int32_t q : failed) lam[q] *= 2.0;
+    pending.swap(failed);
+  }
+  brute.insert(brute.end(), pending.begin(), pending.end());
+  std::sort(brute.begin(), brute.end());
+  if (!brute.empty()) {
+    int mmax = 0;
+    for (int32_t q : brute) mmax = std::max<int>(mmax, (int)(nptr[q + 1] - nptr[q]));
+    BTRY(hipMemcpy(dq.p, brute.data(), sizeof(int32_t) * brute.size(), hipMemcpyHostToDevice));
+    BTRY(launch_knn(dZo, d, dcen, dbp, (int)K, mmax, dnp, dpos, nullptr, dq.p, (int)brute.size()));
+  }
+  return SBV_OK;
+}
+
+}  // namespace
+
+extern "C" sbv_status sbv_build_blocks(const double* X, const double* y, int64_t n, int32_t d,
+                                       const double* beta_build, int64_t n_blocks, int32_t m,
+                                       const sbv_build_opts* opts, sbv_blocks* out) {
+  if (!X || !beta_build || !out) return sbv_internal_fail(SBV_E_INVAL, "X, beta_build and out are required");
+  if (n <= 0 || d <= 0 || d > kMaxDim || n_blocks <= 0 || n_blocks > n || m < 0)
+    return sbv_internal_fail(SBV_E_INVAL, "need n > 0, 0 < d <= 20, 0 < n_blocks <= n, m >= 0");
+  if (n > INT32_MAX - 1 || n_blocks > INT32_MAX / 2) return sbv_internal_fail(SBV_E_INVAL, "n too large");
+  if (m > knn_max_m()) return sbv_internal_fail(SBV_E_INVAL, "m exceeds the neighbour-search capacity");
+  sbv_build_opts o{SBV_KMEANS, 10, 0, 0, 0, 0, 0.0};
+  if (opts) o = *opts;
+  if (o.method != SBV_KMEANS && o.method != SBV_RAC) return sbv_internal_fail(SBV_E_INVAL, "unknown method");
+  if (o.min_bs < 0 || o.max_bs < 0 || (o.max_bs > 0 && o.min_bs > o.max_bs))
+    return sbv_internal_fail(SBV_E_INVAL, "bad size bounds");
+  for (int k = 0; k < d; ++k)
+    if (!(beta_build[k] > 0.0) || !std::isfinite(beta_build[k]))
+      return sbv_internal_fail(SBV_E_INVAL, "beta_build must be positive and finite");
+  for (int64_t i = 0; i < n * d; ++i)
+    if (!std::isfinite(X[i])) return sbv_internal_fail(SBV_E_INVAL, "X has non-finite values");
+  const int lloyd = o.method == SBV_RAC ? 0 : std::max(0, o.lloyd_iters);
+  if (!(o.nns_alpha >= 0.0) && !(o.nns_alpha < 0.0)) return sbv_internal_fail(SBV_E_INVAL, "nns_alpha is NaN");
+  int64_t K = n_blocks;
+
+  // 1. scaling
+  std::vector<double> Z((size_t)n * d);
+  for (int64_t i = 0; i < n; ++i)
+    for (int k = 0; k < d; ++k) Z[i * d + k] = X[i * d + k] / beta_build[k];
+  std::vector<int32_t> lab;
+  sbv_status st = SBV_OK;
+  if (o.n_slabs <= 1) {
+    st = cluster_points(Z, n, d, K, o, o.seed, lloyd, lab);
+    if (st) return st;
+  } else {
+    // Alg. 2: slabs of equal point count along the scaled dimension of largest
+    // extent (the most relevant input); each slab is clustered on its own with
+    // a share of the K blocks proportional to its size
+    int ax = 0;
+    double ext = -1.0;
+    for (int k = 0; k < d; ++k) {
+      double lo = INFINITY, hi = -INFINITY;
+      for (int64_t i = 0; i < n; ++i) {
+        lo = std::min(lo, Z[i * d + k]);
+        hi = std::max(hi, Z[i * d + k]);
+      }
+      if (hi - lo > ext) {
+        ext = hi - lo;
+        ax = k;
+      }
+    }
+    std::vector<int64_t> ids(n);
+    std::iota(ids.begin(), ids.end(), 0);
+    std::stable_sort(ids.begin(), ids.end(), [&](int64_t a, int64_t b) { return Z[a * d + ax] < Z[b * d + ax]; });
+    const int S = (int)std::min<int64_t>(o.n_slabs, K);
+    lab.assign(n, 0);
+    int64_t koff = 0;
+    for (int sl = 0; sl < S; ++sl) {
+      const int64_t i0 = sl * n / S, i1 = (sl + 1) * n / S, ns = i1 - i0;
+      int64_t Ks = std::max<int64_t>(1, (int64_t)std::llround((double)K * ns / n));
+      Ks = std::min(Ks, ns);
+      std::vector<double> Zs((size_t)ns * d);
+      for (int64_t t = 0; t < ns; ++t) std::memcpy(&Zs[t * d], &Z[ids[i0 + t] * d], sizeof(double) * d);
+      std::vector<int32_t> ls;
+      st = cluster_points(Zs, ns, d, Ks, o, o.seed + 0x10000ull * (uint64_t)sl, lloyd, ls);
+      if (st) return st;
+      for (int64_t t = 0; t < ns; ++t) lab[ids[i0 + t]] = (int32_t)(koff + ls[t]);
+      koff += Ks;
+    }
+    K = koff;
+  }
   // 6. random block order
   std::vector<int64_t> order(K), rank_of(K);
   std::iota(order.begin(), order.end(), 0);
@@ -295,7 +430,9 @@ extern "C" sbv_status sbv_build_blocks(const double* X, const double* y, int64_t
   for (int64_t r = 0; r < K; ++r) nptr[r + 1] = nptr[r] + std::min<int64_t>(m, bptr[r]);
   const int64_t nnz = nptr[K];
   if (nnz > INT32_MAX) return sbv_internal_fail(SBV_E_INVAL, "too many conditioning entries");
-  // 8. neighbours on the device
+  // 8. neighbours on the device: the filtered search (expansion factor alpha;
+  //    0 = automatic: 3 from 2048 blocks on, brute force below; < 0 = brute force)
+  const double alpha = o.nns_alpha > 0.0 ? o.nns_alpha : (o.nns_alpha == 0.0 && K >= 2048 ? 3.0 : 0.0);
   std::vector<int32_t> bp32(K + 1), npos(std::max<int64_t>(nnz, 1));
   for (int64_t r = 0; r <= K; ++r) bp32[r] = (int32_t)bptr[r];
   {
@@ -311,7 +448,12 @@ extern "C" sbv_status sbv_build_blocks(const double* X, const double* y, int64_t
     BTRY(hipMemcpy(dcen.p, cen.data(), sizeof(double) * K * d, hipMemcpyHostToDevice));
     BTRY(hipMemcpy(dbp.p, bp32.data(), sizeof(int32_t) * (K + 1), hipMemcpyHostToDevice));
     BTRY(hipMemcpy(dnp.p, nptr.data(), sizeof(int64_t) * (K + 1), hipMemcpyHostToDevice));
-    BTRY(launch_knn(dZo.p, d, dcen.p, dbp.p, (int)K, m, dnp.p, dpos.p, nullptr));
+    if (alpha > 0.0) {
+      st = filtered_knn(Zo, cen, bp32, nptr, n, d, K, alpha, dZo.p, dcen.p, dbp.p, dnp.p, dpos.p);
+      if (st) return st;
+    } else {
+      BTRY(launch_knn(dZo.p, d, dcen.p, dbp.p, (int)K, m, dnp.p, dpos.p, nullptr));
+    }
     BTRY(hipMemcpy(npos.data(), dpos.p, sizeof(int32_t) * std::max<int64_t>(nnz, 1), hipMemcpyDeviceToHost));
   }
   std::vector<int64_t> nidx(std::max<int64_t>(nnz, 1));

@@ -188,6 +188,7 @@ struct Smem {
   T zfull[GRAD ? NTM * kTile : 1];  // all of z = L^{-1} y (GRAD only)
   T xi[NTM * kTile];                // innovations of the conditional simulator
   int la_flag;                      // lookahead: last diagonal step published
+  int next_item;                    // work-queue mode: the item taken by this workgroup
   double isc[kMaxDim];              // exp(-theta_k) of the set being processed
 #ifdef SBV_PHASE_PROFILE
   unsigned long long prof[16];
@@ -1255,7 +1256,16 @@ __global__ __launch_bounds__(NW * 64) void k_block_loglik(const SetDesc* __restr
 #endif
 
   int isc_set = -1;  // set whose coordinate scales sm.isc holds
-  for (int it = blockIdx.x; it < total; it += gridDim.x) {
+  // next item: grid stride, or one atomic increment of the queue per item
+  auto take = [&](int cur) -> int {
+    if (PRE || !L.queue) return cur + gridDim.x;
+    if (tid == 0) sm.next_item = atomicAdd(L.queue, 1);
+    __syncthreads();
+    const int v = sm.next_item;
+    __syncthreads();
+    return v;
+  };
+  for (int it = (PRE || !L.queue) ? (int)blockIdx.x : take(0); it < total; it = take(it)) {
     const WorkItem w = itm[it];
     const SetDesc S = sets[w.set];
     const int d = S.d;
@@ -1998,20 +2008,21 @@ constexpr int nw_of() {
 
 template <typename T, int NTM, int NW>
 static hipError_t launch_t(int grid, bool grad, bool la, const SetDesc* sets, const double* theta,
-                           const WorkItem* items, const int* count, double piv_tau, hipStream_t s) {
+                           const WorkItem* items, const int* count, double piv_tau, hipStream_t s, int* queue) {
   if constexpr (nw_of<T, NW>() != NW) {
-    return launch_t<T, NTM, nw_of<T, NW>()>(grid, grad, la, sets, theta, items, count, piv_tau, s);
+    return launch_t<T, NTM, nw_of<T, NW>()>(grid, grad, la, sets, theta, items, count, piv_tau, s, queue);
   } else {
     constexpr int NWG = NW > 8 ? 8 : NW;  // the gradient kernels keep the 8-wave layout
+    const LargeArgs q{0, 0, nullptr, nullptr, nullptr, queue};
     if (la && !grad)
       hipLaunchKernelGGL((k_block_loglik<T, NTM, NW, false, false, true>), dim3(grid), dim3(NW * 64), 0, s, sets,
-                         theta, items, count, piv_tau, LargeArgs{});
+                         theta, items, count, piv_tau, q);
     else if (grad)
       hipLaunchKernelGGL((k_block_loglik<T, NTM, NWG, true>), dim3(grid), dim3(NWG * 64), 0, s, sets, theta, items,
-                         count, piv_tau, LargeArgs{});
+                         count, piv_tau, q);
     else
       hipLaunchKernelGGL((k_block_loglik<T, NTM, NW, false>), dim3(grid), dim3(NW * 64), 0, s, sets, theta, items,
-                         count, piv_tau, LargeArgs{});
+                         count, piv_tau, q);
     return hipGetLastError();
   }
 }
@@ -2047,9 +2058,9 @@ static hipError_t launch_c(int grid, const SetDesc* sets, const double* theta, c
 
 hipError_t launch_loglik(int prec, int v, int grid, const SetDesc* sets, const double* theta,
                          const WorkItem* items, const int* count, double piv_tau, hipStream_t s, bool grad,
-                         bool lookahead) {
+                         bool lookahead, int* queue) {
   if (grid <= 0) return hipSuccess;
-#define SBV_CALL(T, A, B) launch_t<T, A, B>(grid, grad, lookahead, sets, theta, items, count, piv_tau, s)
+#define SBV_CALL(T, A, B) launch_t<T, A, B>(grid, grad, lookahead, sets, theta, items, count, piv_tau, s, queue)
   if (prec == 0) {
     SBV_VARIANT_SWITCH(double, SBV_CALL)
   } else {

@@ -26,11 +26,6 @@
 #include "../../include/sbv.h"
 #include "sbv_internal.h"
 
-namespace sbv {
-hipError_t launch_knn(const double* Z, int d, const double* cen, const int32_t* bptr, int K, int m,
-                      const int64_t* nn_ptr, int32_t* nn_pos, hipStream_t s);
-int knn_max_m();
-}  // namespace sbv
 
 sbv_status sbv_internal_fail(sbv_status st, const char* msg);
 sbv_status sbv_internal_view(sbv_blocks h, sbv::HandleView* v);

@@ -74,6 +74,11 @@ struct LargeArgs {
   void* W;
   void* z;
   void* Lpp;
+  // Register kernels only: when set, workgroups take their items from this
+  // device counter (one atomic increment per item, starting at 0) instead of
+  // striding by the grid size -- one persistent launch can then serve every
+  // item of a list whatever the number of resident workgroups.
+  int* queue;
 };
 
 // Prefix length p of a block with joint size nA and m_i conditioning points
@@ -90,7 +95,7 @@ inline int large_prefix(int nA, int mi) {
 // items[blockIdx.x + k*gridDim.x] while the index is below *count.
 hipError_t launch_loglik(int prec, int variant, int grid, const SetDesc* sets, const double* theta,
                          const WorkItem* items, const int* count, double piv_tau, hipStream_t s,
-                         bool grad = false, bool lookahead = false);
+                         bool grad = false, bool lookahead = false, int* queue = nullptr);
 hipError_t launch_contract(int prec, int variant, int grid, const SetDesc* sets, const double* theta,
                            const WorkItem* items, const int* count, hipStream_t s);
 hipError_t launch_sample(int variant, int grid, const SetDesc* sets, const double* theta,
@@ -143,6 +148,20 @@ struct HandleView {
   const int64_t* block_pts_host;  // host, n: original id of each ordered position
   int64_t n;
 };
+
+// Neighbour search of the builder (build_kernels.hip): brute force over the
+// points of earlier blocks for queries 0..K-1 or the ascending ranks in qlist,
+// and the two steps of the filtered search (coarse candidate blocks, fine
+// candidate points with its exactness status).
+hipError_t launch_knn(const double* Z, int d, const double* cen, const int32_t* bptr, int K, int m,
+                      const int64_t* nn_ptr, int32_t* nn_pos, hipStream_t s, const int32_t* qlist = nullptr,
+                      int nq = 0);
+hipError_t launch_knn_coarse(const double* cen, const double* rad, int d, const int32_t* qlist, int nq,
+                             const double* lam, int cap, int32_t* cand, int32_t* ccount, hipStream_t s);
+hipError_t launch_knn_fine(const double* Z, int d, const double* cen, const int32_t* bptr, const int32_t* qlist,
+                           int nq, const double* lam, int cap, const int32_t* cand, const int32_t* ccount,
+                           const int64_t* nn_ptr, int32_t* nn_pos, int32_t* status, hipStream_t s);
+int knn_max_m();
 
 // Dense covariance matrix between two point lists (device buffers; theta on
 // the device, d + 2 log-parameters).

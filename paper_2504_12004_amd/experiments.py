@@ -279,38 +279,48 @@ def c3(out_path, reps=3):
     stream = torch.cuda.current_stream()
     th_all = torch.tensor(np.concatenate(ths), dtype=torch.float64, device=dev)
     offs = np.r_[0, np.cumsum([len(t) for t in ths])]
-    for name, prec in (("fp32", sbv.SBV_FP32), ("fp64", sbv.SBV_FP64)):
-        tiles = sbv.sbv_autotune(hs, ths, tns, prec, reps=2)
-        out_b = torch.empty(64, dtype=torch.float64, device=dev)
-        out_s = torch.empty(64, dtype=torch.float64, device=dev)
-        for _ in range(2):
-            sbv.sbv_eval_graph_dev(hs, th_all, tns, out_b, prec, stream=stream)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def timed(fn):
+        fn()
         torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
         for _ in range(reps):
-            sbv.sbv_eval_graph_dev(hs, th_all, tns, out_b, prec, stream=stream)
+            fn()
         e1.record(stream)
         torch.cuda.synchronize()
-        t_b = e0.elapsed_time(e1) / reps
+        return e0.elapsed_time(e1) / reps
+
+    for name, prec in (("fp32", sbv.SBV_FP32), ("fp64", sbv.SBV_FP64)):
+        out_b = torch.empty(64, dtype=torch.float64, device=dev)
+        out_s = torch.empty(64, dtype=torch.float64, device=dev)
+
+        def batched():
+            sbv.sbv_eval_graph_dev(hs, th_all, tns, out_b, prec, stream=stream)
 
         def seq():
             for j in range(64):
                 sbv.sbv_loglik_dev(hs[j], th_all[offs[j]:offs[j + 1]], tns[j], out_s[j:j + 1], prec, stream)
-        seq()
-        torch.cuda.synchronize()
-        e0.record(stream)
-        for _ in range(reps):
-            seq()
-        e1.record(stream)
-        torch.cuda.synchronize()
-        t_s = e0.elapsed_time(e1) / reps
+        # 1. the same kernel for every block in both runs (default variants):
+        #    the batched values must equal the per-dataset ones bit for bit
+        t_b0, t_s0 = timed(batched), timed(seq)
         ob, os_ = out_b.cpu().numpy(), out_s.cpu().numpy()
-        res[name] = {"batched_graph_ms": t_b, "sequential_ms": t_s, "speedup": t_s / t_b,
+        bitwise = bool(np.array_equal(ob, os_))
+        # 2. both autotuned (the combined plan and every per-dataset plan)
+        tiles = sbv.sbv_autotune(hs, ths, tns, prec, reps=2)
+        for j in range(64):
+            sbv.sbv_autotune([hs[j]], [ths[j]], [tns[j]], prec, reps=2)
+        t_b, t_s = timed(batched), timed(seq)
+        ob2, os2 = out_b.cpu().numpy(), out_s.cpu().numpy()
+        res[name] = {"default_variants": {"batched_graph_ms": t_b0, "sequential_ms": t_s0, "speedup": t_s0 / t_b0,
+                                          "bitwise_equal": bitwise},
+                     "autotuned": {"batched_graph_ms": t_b, "sequential_ms": t_s, "speedup": t_s / t_b,
+                                   "max_rel_diff_batched_vs_sequential":
+                                       float(np.max(np.abs(ob2 - os2) / np.abs(os2)))},
                      "batched_algorithmic_tflops": float(np.sum(flops)) / (t_b * 1e-3) / 1e12,
-                     "max_rel_diff_batched_vs_sequential": float(np.max(np.abs(ob - os_) / np.abs(os_))),
                      "autotuned_tiles": [int(t) for t in tiles]}
-        log(f"{name}: batched graph {t_b:.1f} ms, sequential {t_s:.1f} ms, "
+        log(f"{name}: default variants batched {t_b0:.1f} ms vs sequential {t_s0:.1f} ms (bitwise {bitwise}); "
+            f"autotuned batched {t_b:.1f} ms vs sequential {t_s:.1f} ms, "
             f"{res[name]['batched_algorithmic_tflops']:.2f} TFLOP/s")
     for b in hs:
         b.free()

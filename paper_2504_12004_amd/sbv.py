@@ -34,7 +34,7 @@ class SBVError(RuntimeError):
 
 class sbv_build_opts(C.Structure):
     _fields_ = [("method", C.c_int32), ("lloyd_iters", C.c_int32), ("min_bs", C.c_int32),
-                ("max_bs", C.c_int32), ("reserved", C.c_int32), ("seed", C.c_uint64)]
+                ("max_bs", C.c_int32), ("n_slabs", C.c_int32), ("seed", C.c_uint64), ("nns_alpha", C.c_double)]
 
 
 class sbv_fit_opts(C.Structure):
@@ -109,7 +109,8 @@ def lib():
                                          C.c_int32, C.c_int32, C.c_void_p, C.c_void_p]),
         "sbv_eval_graph_dev": (C.c_int, [C.POINTER(_h), C.c_int32, C.c_void_p, _i32, C.c_int32, C.c_int32,
                                          C.c_void_p, C.c_void_p, C.c_void_p]),
-        "sbv_autotune": (C.c_int, [C.POINTER(_h), C.c_int32, _i32, _d, C.c_int32, C.c_int32, _i32, _i32, _i32]),
+        "sbv_autotune": (C.c_int, [C.POINTER(_h), C.c_int32, _i32, _d, C.c_int32, C.c_int32, _i32, _i32, _i32,
+                                   _i32]),
         "sbv_timing_enable": (C.c_int, [C.c_int32]),
         "sbv_timing_read": (C.c_int, [C.c_int32, _i32, _d, _i64]),
         "sbv_plan_flops": (C.c_int, [C.POINTER(_h), C.c_int32, _i32, _d, _i32, _i32]),
@@ -183,12 +184,13 @@ def sbv_blocks_import(X, y, block_ptr, block_pts, nn_ptr, nn_idx):
 
 
 def sbv_build_blocks(X, y, beta_build, n_blocks, m, method=SBV_KMEANS, lloyd_iters=10, min_bs=0, max_bs=0,
-                     seed=0):
+                     seed=0, n_slabs=1, nns_alpha=0.0):
     X = _c64(X)
     n, d = X.shape
     y = None if y is None else _c64(y)
     bb = _c64(beta_build)
-    o = sbv_build_opts(int(method), int(lloyd_iters), int(min_bs), int(max_bs), 0, int(seed))
+    o = sbv_build_opts(int(method), int(lloyd_iters), int(min_bs), int(max_bs), int(n_slabs), int(seed),
+                       float(nns_alpha))
     h = C.c_void_p()
     _check(lib().sbv_build_blocks(_p(X), _p(y) if y is not None else None, n, d, _p(bb), int(n_blocks), int(m),
                                   C.byref(o), C.byref(h)))
@@ -493,18 +495,20 @@ def sbv_eval_graph_dev(sets, theta_dev, two_nu, out_dev, prec=SBV_FP64, grad_dev
 
 def sbv_autotune(sets, theta, two_nu, prec=SBV_FP64, reps=2, with_schedule=False):
     """Chosen tile capacity per size bucket; with_schedule=True also returns
-    the per-bucket lookahead choice (1 = lookahead schedule) and the waves per
-    workgroup of the chosen kernel."""
+    the per-bucket lookahead choice (1 = lookahead schedule), the waves per
+    workgroup of the chosen kernel, and whether the single persistent launch
+    won over per-bucket launches."""
     hs, ns = _handles(sets)
     th = _c64(np.concatenate([np.ravel(t) for t in theta]) if isinstance(theta, (list, tuple)) else theta)
     tn = np.ascontiguousarray(np.broadcast_to(np.asarray(two_nu, np.int32), (ns,)), dtype=np.int32)
     ch = np.zeros(16, np.int32)
     la = np.zeros(16, np.int32)
     wv = np.zeros(16, np.int32)
+    pers = C.c_int32()
     _check(lib().sbv_autotune(hs, ns, _p(tn, _i32), _p(th), int(prec), int(reps), _p(ch, _i32), _p(la, _i32),
-                              _p(wv, _i32)))
+                              _p(wv, _i32), C.byref(pers)))
     if with_schedule:
-        return ch[ch > 0], la[ch > 0], wv[ch > 0]
+        return ch[ch > 0], la[ch > 0], wv[ch > 0], bool(pers.value)
     return ch[ch > 0]
 
 
@@ -535,7 +539,7 @@ def sbv_pred_build(b, Xp, beta_build, n_blocks, m_pred, method=SBV_KMEANS, lloyd
                    seed=0):
     Xp = _c64(Xp)
     bb = _c64(beta_build)
-    o = sbv_build_opts(int(method), int(lloyd_iters), int(min_bs), int(max_bs), 0, int(seed))
+    o = sbv_build_opts(int(method), int(lloyd_iters), int(min_bs), int(max_bs), 1, int(seed), -1.0)
     h = C.c_void_p()
     _check(lib().sbv_pred_build(b.handle, _p(Xp), Xp.shape[0], _p(bb), int(n_blocks), int(m_pred), C.byref(o),
                                 C.byref(h)))

@@ -83,3 +83,39 @@ def test_autotune_keeps_values(sbv, batch):
     assert len(chosen) >= 1
     after = sbv.sbv_loglik(hs, ths, tns)
     assert np.all(np.abs(after - before) <= 1e-13 * np.abs(before))
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-10), (1, 1e-4)])
+def test_persistent_single_launch(sbv, batch, prec, tol, monkeypatch):
+    """SBV_PERSISTENT=1: every register-path block of every set goes through
+    one launch whose workgroups take blocks from a device counter, longest
+    first; values match the oracle, and its captured graph replays equal the
+    eager evaluation (the counter is reset by a kernel inside the graph)."""
+    import torch
+    hs, ths, tns, refs = batch
+    monkeypatch.setenv("SBV_PERSISTENT", "1")
+    got = sbv.sbv_loglik(hs, ths, tns, prec)
+    assert np.all(np.abs(got - refs) <= tol * np.abs(refs))
+    dev = torch.device("cuda:0")
+    th = torch.tensor(np.concatenate(ths), dtype=torch.float64, device=dev)
+    out_e = torch.empty(len(hs), dtype=torch.float64, device=dev)
+    out_g = torch.empty(len(hs), dtype=torch.float64, device=dev)
+    sbv.sbv_loglik_dev(hs, th, tns, out_e, prec)
+    torch.cuda.synchronize()
+    eager = out_e.cpu().numpy().copy()
+    assert np.array_equal(eager, got)
+    # a graph captured in persistent mode (its own plan: a fresh handle list order)
+    order = [3, 2, 1, 0]
+    hs2 = [hs[i] for i in order]
+    th2 = torch.tensor(np.concatenate([ths[i] for i in order]), dtype=torch.float64, device=dev)
+    tn2 = [tns[i] for i in order]
+    sbv.sbv_loglik_dev(hs2, th2, tn2, out_e, prec)
+    torch.cuda.synchronize()
+    eager2 = out_e.cpu().numpy().copy()
+    assert np.all(np.abs(eager2 - refs[order]) <= tol * np.abs(refs[order]))
+    for rep in range(3):
+        sbv.sbv_eval_graph_dev(hs2, th2, tn2, out_g, prec)
+        torch.cuda.synchronize()
+        assert np.array_equal(out_g.cpu().numpy(), eager2), rep
+        sbv.sbv_loglik_dev(hs, th, tns, out_e, prec)  # eager work of another plan in between
+        torch.cuda.synchronize()

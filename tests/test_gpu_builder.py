@@ -120,3 +120,46 @@ def test_builder_neighbours_at_full_size(sbv):
         # everything strictly closer than the m-th distance is in the set
         inside = np.nonzero(d2 < kth * (1 - 1e-12))[0]
         assert set(inside.tolist()) <= set(pj.tolist()), r
+
+
+def test_filtered_neighbour_search_equals_brute_force(sbv):
+    """The filtered search (Alg. 4 with the threshold of Eq.
+    (distancethreashold), conservative candidate test, retries at twice the
+    threshold) gives exactly the brute-force structure, for the default
+    expansion factor and for one so small that most queries need retries."""
+    rng = np.random.default_rng(41)
+    X = rng.random((20000, 10))
+    bb = np.exp(rng.uniform(np.log(0.1), np.log(2.0), 10))
+    ref = _structure(sbv, sbv.sbv_build_blocks(X, None, bb, 1000, 100, lloyd_iters=3, min_bs=5, max_bs=40, seed=6,
+                                               nns_alpha=-1.0))
+    for alpha in (3.0, 0.4):
+        B = sbv.sbv_build_blocks(X, None, bb, 1000, 100, lloyd_iters=3, min_bs=5, max_bs=40, seed=6, nns_alpha=alpha)
+        S = _structure(sbv, B)
+        for a, b in ((S.block_ptr, ref.block_ptr), (S.block_pts, ref.block_pts), (S.nn_ptr, ref.nn_ptr),
+                     (S.nn_idx, ref.nn_idx)):
+            assert np.array_equal(a, b), alpha
+        B.free()
+
+
+def test_slabs_keep_blocks_inside_their_slab(sbv):
+    """n_slabs = 4 (Alg. 2): points are cut into four equal-count slabs along
+    the scaled dimension of largest extent and every block lies in one slab;
+    neighbour sets stay exact and may cross slabs."""
+    rng = np.random.default_rng(42)
+    X = rng.random((6000, 5))
+    bb = np.array([0.2, 1.0, 0.5, 2.0, 0.8])
+    B = sbv.sbv_build_blocks(X, None, bb, 300, 40, lloyd_iters=3, min_bs=5, max_bs=40, seed=7, n_slabs=4)
+    S = _structure(sbv, B)
+    Z = X / bb
+    ax = int(np.argmax(Z.max(0) - Z.min(0)))
+    order = np.argsort(Z[:, ax], kind="stable")
+    slab = np.empty(6000, np.int64)
+    for s in range(4):
+        slab[order[s * 6000 // 4:(s + 1) * 6000 // 4]] = s
+    for r in range(S.K):
+        Bk, _ = S.block(r)
+        assert len(np.unique(slab[Bk])) == 1, r
+    sizes = np.diff(S.block_ptr)
+    assert sizes.min() >= 5 and sizes.max() <= 40
+    _check_knn(X, bb, S, 40)
+    B.free()
