@@ -101,7 +101,7 @@ def main():
     for name, prec in (("fp64", sbv.SBV_FP64), ("fp32", sbv.SBV_FP32)):
         ch, la, wv, pc = sbv.sbv_autotune([B], theta_true, two_nu, prec, reps=3, with_schedule=True)
         tuned[name] = [int(t) for t in ch]
-        sched[name] = [("lookahead" if x else "plain") + f"/{int(v)}w" for x, v in zip(la, wv)]
+        sched[name] = [("lookahead" if x else "plain") + f"/{int(v)} waves per CU" for x, v in zip(la, wv)]
         pers_choice[name] = "persistent single launch" if pc else "one launch per size bucket"
     log(f"autotuned tiles per bucket: {tuned}, schedules {sched}")
 

@@ -337,8 +337,9 @@ sbv_status sbv_eval_graph_dev(const sbv_blocks* sets, int32_t n_sets, const doub
  * bucket, longest bucket first; chosen_lookahead (optional, 16 entries) 1
  * where the lookahead schedule won, else 0 (always 0 for the large-block
  * bucket, which has a single schedule); chosen_waves (optional, 16 entries)
- * the waves per workgroup of the chosen kernel (16-wave kernels exist for
- * FP32 only).  Then whole evaluations with one launch per size bucket are
+ * the waves per compute unit of the chosen kernel (waves per workgroup times
+ * the workgroups it is built to share a unit with; the 16-wave kernels and the
+ * two-workgroups-per-unit kernels exist for FP32 only).  Then whole evaluations with one launch per size bucket are
  * timed against ONE persistent launch for all register-path blocks of all
  * sets (the largest chosen variant, workgroups taking blocks longest first
  * from a device counter); chosen_persistent (optional) receives 1 when the

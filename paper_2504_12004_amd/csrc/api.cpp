@@ -887,8 +887,10 @@ sbv_status sbv_autotune(const sbv_blocks* sets, int32_t n_sets, const int32_t* t
     B.la[pk] = bestla;
     if (chosen_tiles) chosen_tiles[bi] = variant(bestv).ntm;
     if (chosen_lookahead) chosen_lookahead[bi] = bestla ? 1 : 0;
-    // (FP64 requests for a 16-wave variant run the 8-wave kernel)
-    if (chosen_waves) chosen_waves[bi] = (pk == 0 && variant(bestv).nw > 8) ? 8 : variant(bestv).nw;
+    // waves per compute unit: waves per workgroup times workgroups per unit
+    // (FP64 requests for the 16-wave and occupancy-2 variants run the 8-wave kernel)
+    if (chosen_waves)
+      chosen_waves[bi] = pk == 0 ? std::min(variant(bestv).nw, 8) : variant(bestv).nw * std::max(variant(bestv).occ, 1);
     ++bi;
   }
   // whole evaluations: per-bucket launches against the persistent launch

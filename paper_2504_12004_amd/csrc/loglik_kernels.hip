@@ -1237,8 +1237,9 @@ __device__ __forceinline__ void panel_adjoint(SM& sm, int lane, int nt, int mi, 
 // were eliminated by k_block_prefix, which left L_RP and z_P in the workspace
 // window L; this kernel factors the trailing NTM tiles (local point l is joint
 // point l + 16p) after applying the p prefix updates.
-template <typename T, int NTM, int NW, bool GRAD, bool SAMPLE = false, bool LA = false, bool PRE = false>
-__global__ __launch_bounds__(NW * 64) void k_block_loglik(const SetDesc* __restrict__ sets,
+template <typename T, int NTM, int NW, bool GRAD, bool SAMPLE = false, bool LA = false, bool PRE = false,
+          int OCC = 1>
+__global__ __launch_bounds__(NW * 64, OCC > 1 ? OCC * NW / 4 : 1) void k_block_loglik(const SetDesc* __restrict__ sets,
                                                           const double* __restrict__ theta,
                                                           const WorkItem* __restrict__ items,
                                                           const int* __restrict__ count,
@@ -1987,7 +1988,12 @@ __global__ __launch_bounds__(NW * 64) void k_block_contract_stream(const SetDesc
 // latency, 128 registers each; the FP64 tiles do not fit 128 registers, so an
 // FP64 request for it runs the 8-wave kernel).  The autotuner may pick any
 // variant at or above a bucket's smallest fitting one.
-static const Variant kVariants[] = {{4, 2}, {8, 4}, {12, 8}, {14, 8}, {14, 16}, {16, 8}, {16, 16}, {17, 8}};
+// The occupancy-2 variants (FP32 only, like the 16-wave ones) cap an 8-wave
+// workgroup at 128 registers per lane so that two blocks share a compute
+// unit and one block's serial diagonal factorisations run beside the other's
+// trailing updates.
+static const Variant kVariants[] = {{4, 2},      {8, 4},  {12, 8},     {14, 8},  {14, 16},
+                                    {14, 8, 2},  {16, 8}, {16, 16},    {16, 8, 2}, {17, 8}};
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
 int n_variants() { return kNumVariants; }
@@ -2006,23 +2012,23 @@ constexpr int nw_of() {
   return (NW > 8 && sizeof(T) == 8) ? 8 : NW;
 }
 
-template <typename T, int NTM, int NW>
+template <typename T, int NTM, int NW, int OCC = 1>
 static hipError_t launch_t(int grid, bool grad, bool la, const SetDesc* sets, const double* theta,
                            const WorkItem* items, const int* count, double piv_tau, hipStream_t s, int* queue) {
-  if constexpr (nw_of<T, NW>() != NW) {
-    return launch_t<T, NTM, nw_of<T, NW>()>(grid, grad, la, sets, theta, items, count, piv_tau, s, queue);
+  if constexpr (nw_of<T, NW>() != NW || (OCC > 1 && sizeof(T) == 8)) {
+    return launch_t<T, NTM, nw_of<T, NW>(), 1>(grid, grad, la, sets, theta, items, count, piv_tau, s, queue);
   } else {
     constexpr int NWG = NW > 8 ? 8 : NW;  // the gradient kernels keep the 8-wave layout
     const LargeArgs q{0, 0, nullptr, nullptr, nullptr, queue};
     if (la && !grad)
-      hipLaunchKernelGGL((k_block_loglik<T, NTM, NW, false, false, true>), dim3(grid), dim3(NW * 64), 0, s, sets,
-                         theta, items, count, piv_tau, q);
+      hipLaunchKernelGGL((k_block_loglik<T, NTM, NW, false, false, true, false, OCC>), dim3(grid), dim3(NW * 64), 0,
+                         s, sets, theta, items, count, piv_tau, q);
     else if (grad)
       hipLaunchKernelGGL((k_block_loglik<T, NTM, NWG, true>), dim3(grid), dim3(NWG * 64), 0, s, sets, theta, items,
                          count, piv_tau, q);
     else
-      hipLaunchKernelGGL((k_block_loglik<T, NTM, NW, false>), dim3(grid), dim3(NW * 64), 0, s, sets, theta, items,
-                         count, piv_tau, q);
+      hipLaunchKernelGGL((k_block_loglik<T, NTM, NW, false, false, false, false, OCC>), dim3(grid), dim3(NW * 64), 0,
+                         s, sets, theta, items, count, piv_tau, q);
     return hipGetLastError();
   }
 }
@@ -2044,23 +2050,25 @@ static hipError_t launch_c(int grid, const SetDesc* sets, const double* theta, c
   return hipGetLastError();
 }
 
-#define SBV_VARIANT_SWITCH(T, CALL)   \
-  switch (v) {                        \
-    case 0: return CALL(T, 4, 2);     \
-    case 1: return CALL(T, 8, 4);     \
-    case 2: return CALL(T, 12, 8);    \
-    case 3: return CALL(T, 14, 8);    \
-    case 4: return CALL(T, 14, 16);   \
-    case 5: return CALL(T, 16, 8);    \
-    case 6: return CALL(T, 16, 16);   \
-    case 7: return CALL(T, 17, 8);    \
+#define SBV_VARIANT_SWITCH(T, CALL)      \
+  switch (v) {                           \
+    case 0: return CALL(T, 4, 2, 1);     \
+    case 1: return CALL(T, 8, 4, 1);     \
+    case 2: return CALL(T, 12, 8, 1);    \
+    case 3: return CALL(T, 14, 8, 1);    \
+    case 4: return CALL(T, 14, 16, 1);   \
+    case 5: return CALL(T, 14, 8, 2);    \
+    case 6: return CALL(T, 16, 8, 1);    \
+    case 7: return CALL(T, 16, 16, 1);   \
+    case 8: return CALL(T, 16, 8, 2);    \
+    case 9: return CALL(T, 17, 8, 1);    \
   }
 
 hipError_t launch_loglik(int prec, int v, int grid, const SetDesc* sets, const double* theta,
                          const WorkItem* items, const int* count, double piv_tau, hipStream_t s, bool grad,
                          bool lookahead, int* queue) {
   if (grid <= 0) return hipSuccess;
-#define SBV_CALL(T, A, B) launch_t<T, A, B>(grid, grad, lookahead, sets, theta, items, count, piv_tau, s, queue)
+#define SBV_CALL(T, A, B, C) launch_t<T, A, B, C>(grid, grad, lookahead, sets, theta, items, count, piv_tau, s, queue)
   if (prec == 0) {
     SBV_VARIANT_SWITCH(double, SBV_CALL)
   } else {
@@ -2114,7 +2122,7 @@ hipError_t launch_large_grad(int prec, int grid, const SetDesc* sets, const doub
 hipError_t launch_sample(int v, int grid, const SetDesc* sets, const double* theta, const WorkItem* items,
                          const int* count, hipStream_t s) {
   if (grid <= 0) return hipSuccess;
-#define SBV_CALL(T, A, B) launch_s<T, A, B>(grid, sets, theta, items, count, s)
+#define SBV_CALL(T, A, B, C) launch_s<T, A, B>(grid, sets, theta, items, count, s)
   SBV_VARIANT_SWITCH(double, SBV_CALL)
 #undef SBV_CALL
   return hipErrorInvalidValue;
@@ -2123,7 +2131,7 @@ hipError_t launch_sample(int v, int grid, const SetDesc* sets, const double* the
 hipError_t launch_contract(int prec, int v, int grid, const SetDesc* sets, const double* theta,
                            const WorkItem* items, const int* count, hipStream_t s) {
   if (grid <= 0) return hipSuccess;
-#define SBV_CALL(T, A, B) launch_c<T, A, (B < 4 ? 4 : B)>(grid, sets, theta, items, count, s)
+#define SBV_CALL(T, A, B, C) launch_c<T, A, (B < 4 ? 4 : B)>(grid, sets, theta, items, count, s)
   if (prec == 0) {
     SBV_VARIANT_SWITCH(double, SBV_CALL)
   } else {

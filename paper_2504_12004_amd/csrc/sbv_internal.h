@@ -41,10 +41,12 @@ struct WorkItem {
   int32_t block;
 };
 
-// Kernel variant: register-tile capacity NTM tiles per side, NW waves.
+// Kernel variant: register-tile capacity NTM tiles per side, NW waves, and
+// occ workgroups meant to share a compute unit (registers capped to fit).
 struct Variant {
   int ntm;
   int nw;
+  int occ = 1;
 };
 
 // Blocks whose joint size exceeds the register capacity of the largest

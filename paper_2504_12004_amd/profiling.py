@@ -42,9 +42,27 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def passes(out):
+LARGE_BENCH_ARGS = ["--steps", "1", "--warmup", "1", "--no-cpu-baseline", "--fit-evals", "0", "--large-steps", "2"]
+
+
+def passes(out, workload="uneven_1m"):
     py = sys.executable
     bench = os.path.join(ROOT, "bench.py")
+    if workload == "m400_5m":
+        # the m = 400, n = 5e6 leg: kernel trace and the two HBM byte counters
+        # (the copy calibration is shared with the headline workload's passes)
+        return [
+            ("trace", 600, ["rocprofv3", "--kernel-trace", "--stats", "-d", f"{out}/trace", "-o", "bench", "--",
+                            py, bench] + LARGE_BENCH_ARGS),
+            ("fetch", 600, ["rocprofv3", "--pmc", "FETCH_SIZE", "-d", f"{out}/fetch", "-o", "bench", "--",
+                            py, bench] + LARGE_BENCH_ARGS),
+            ("write", 600, ["rocprofv3", "--pmc", "WRITE_SIZE", "-d", f"{out}/write", "-o", "bench", "--",
+                            py, bench] + LARGE_BENCH_ARGS),
+            ("copy_fetch", 200, ["rocprofv3", "--pmc", "FETCH_SIZE", "-d", f"{out}/copy_fetch", "-o", "copy", "--",
+                                 py, bench, "--copy-calibration"]),
+            ("copy_write", 200, ["rocprofv3", "--pmc", "WRITE_SIZE", "-d", f"{out}/copy_write", "-o", "copy", "--",
+                                 py, bench, "--copy-calibration"]),
+        ]
     return [
         ("trace", 400, ["rocprofv3", "--kernel-trace", "--stats", "-d", f"{out}/trace", "-o", "bench", "--",
                         py, bench] + BENCH_ARGS),
@@ -60,10 +78,10 @@ def passes(out):
           + COUNTER_BENCH_ARGS) for name, ctrs in SQ_PASSES.items()]
 
 
-def run(out):
+def run(out, workload="uneven_1m"):
     os.makedirs(out, exist_ok=True)
     env = dict(os.environ, TMPDIR="/tmp")
-    for name, limit, cmd in passes(out):
+    for name, limit, cmd in passes(out, workload):
         print(f"[prof] {name}: {' '.join(cmd)}", flush=True)
         with open(f"{out}/{name}.out", "w") as fo, open(f"{out}/{name}.err", "w") as fe:
             try:
@@ -77,7 +95,7 @@ def run(out):
             return rc
     with open(f"{out}/commands.json", "w") as f:
         json.dump({n: " ".join(c).replace(ROOT + "/", "").replace(sys.executable, "python")
-                   for n, _, c in passes(out)}, f, indent=1)
+                   for n, _, c in passes(out, workload)}, f, indent=1)
     return 0
 
 
@@ -224,17 +242,92 @@ def summarize(out, write_dir):
     return 0
 
 
+def summarize_large(out, write_dir):
+    """Summary of the m = 400 leg: the prefix-elimination kernel and the
+    trailing register kernel of the large path, per evaluation."""
+    cmds = {}
+    if os.path.exists(f"{out}/commands.json"):
+        with open(f"{out}/commands.json") as f:
+            cmds = json.load(f)
+    tr = _db(f"{out}/trace")
+    bench_line = None
+    if os.path.exists(f"{out}/trace.out"):
+        with open(f"{out}/trace.out") as f:
+            for line in f:
+                if line.startswith("{"):
+                    bench_line = json.loads(line)
+    big = bench_line["extra"]["m400_5m"] if bench_line else None
+    # kernels of the large path, FP64 forward (the prefix kernel and the
+    # register kernel in large-block mode: last template flag true)
+    rows = list(tr.execute("select name, duration from kernels order by dispatch_id"))
+
+    def kind(name):
+        if "k_block_prefix<double" in name:
+            return "prefix"
+        if "k_block_loglik<double, 17, 8, false, false, false, true>" in name:
+            return "trailing"
+        return None
+    per = {}
+    for name, dur in rows:
+        k = kind(name)
+        if k:
+            per.setdefault(k, []).append(dur)
+    fetch = _counter(_db(f"{out}/fetch"), "FETCH_SIZE")
+    write = _counter(_db(f"{out}/write"), "WRITE_SIZE")
+    cf = _counter(_db(f"{out}/copy_fetch"), "FETCH_SIZE")
+    cw = _counter(_db(f"{out}/copy_write"), "WRITE_SIZE")
+    ck = max(cf, key=lambda k: sum(cf[k]) / len(cf[k]))
+    f_scale = (1 << 30) / (sum(cf[ck]) / len(cf[ck]) * 1024)
+    w_scale = (1 << 30) / (sum(cw[ck]) / len(cw[ck]) * 1024)
+
+    def bytes_of(counter, scale, k):
+        v = [x for (name, _), vals in counter.items() if kind(name) == k for x in vals]
+        return (sum(v) * 1024 * scale, len(v)) if v else (None, 0)
+    L = ["# Large-set path on m400_5m (n = 5e6, d = 10, K = 2.5e5, m = 400, FP64)\n",
+         "Made by `python -m paper_2504_12004_amd.profiling run --workload m400_5m` then "
+         "`... summarize --workload m400_5m`, which ran:\n"]
+    for k in ("trace", "fetch", "write", "copy_fetch", "copy_write"):
+        if k in cmds:
+            L.append(f"- {k}: `{cmds[k]}`")
+    L += ["", "The FP64 evaluations of the leg (1 warm-up + 2 timed, plus the gradient runs that also", 
+          "launch the prefix kernel) are all in the trace; the table lists every FP64 forward launch.", "",
+          "| kernel | launches | total ms | avg ms | FETCH GB | WRITE GB |", "|---|---|---|---|---|---|"]
+    res = {"kernel_source_hash": kernel_source_hash()}
+    for k, label in (("prefix", "k_block_prefix<double, 8>"),
+                     ("trailing", "k_block_loglik<double, 17, 8, ..., large-block mode>")):
+        d = per.get(k, [])
+        fb, nf = bytes_of(fetch, f_scale, k)
+        wb, nw = bytes_of(write, w_scale, k)
+        L.append(f"| `{label}` | {len(d)} | {sum(d) / 1e6:.1f} | {sum(d) / max(len(d), 1) / 1e6:.3f} | "
+                 f"{(fb or 0) / 1e9:.2f} ({nf} launches) | {(wb or 0) / 1e9:.2f} ({nw} launches) |")
+        res[k] = {"launches": len(d), "total_ms": sum(d) / 1e6, "fetch_bytes": fb, "write_bytes": wb,
+                  "counter_launches": nf}
+    if big:
+        L += ["", f"- benchmark (same run): FP64 {big['fp64']['ms_per_eval']:.1f} ms per evaluation, "
+              f"{big['algorithmic_tflop_per_eval']:.3f} TFLOP algorithmic per evaluation, "
+              f"{big['fp64']['total_algorithmic_tflops']:.2f} TFLOP/s = "
+              f"{big['fp64']['total_algorithmic_tflops'] / 78.6:.3f} of the FP64 peak"]
+    with open(os.path.join(write_dir, "k_block_large_m400_5m.md"), "w") as f:
+        f.write("\n".join(L) + "\n")
+    with open(os.path.join(write_dir, "k_block_large_m400_5m.json"), "w") as f:
+        json.dump(res, f, indent=1)
+    print("\n".join(L))
+    return 0
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("what", choices=["run", "summarize", "all"])
-    ap.add_argument("--out", default=os.path.join(ROOT, "prof_raw"))
+    ap.add_argument("--out", default=None)
     ap.add_argument("--write", default=os.path.join(ROOT, "profiles"))
+    ap.add_argument("--workload", choices=["uneven_1m", "m400_5m"], default="uneven_1m")
     a = ap.parse_args()
+    out = a.out or os.path.join(ROOT, "prof_raw" if a.workload == "uneven_1m" else "prof_raw_m400")
     rc = 0
     if a.what in ("run", "all"):
-        rc = run(a.out)
+        rc = run(out, a.workload)
     if rc == 0 and a.what in ("summarize", "all"):
-        rc = summarize(a.out, a.write)
+        rc = summarize(out, a.write) if a.workload == "uneven_1m" else summarize_large(out, a.write)
     sys.exit(rc)
 
 
