@@ -68,7 +68,7 @@ def main():
 
     import torch
 
-    from paper_2504_12004_amd import sbv, synth
+    from paper_2504_12004_amd import sbv, synth, workloads
 
     dev = torch.device("cuda:0")
     torch.cuda.init()
@@ -88,7 +88,7 @@ def main():
     # observations: the device Vecchia simulator at the true parameters on an
     # independent generating structure (own seed, m_gen >= m)
     t0 = time.perf_counter()
-    y_d = simulate(sbv, torch, dev, X, theta_true, xi, two_nu, w)
+    y_d = workloads.simulate(sbv, torch, dev, X, theta_true, xi, two_nu, w)
     sbv.sbv_blocks_set_y_dev(B, y_d)
     torch.cuda.synchronize()
     y_host = y_d.cpu().numpy()
@@ -234,36 +234,17 @@ def main():
     print(json.dumps(res), flush=True)
 
 
-def simulate(sbv, torch, dev, X, theta, xi, two_nu, w):
-    """Observations at the true parameters: the device conditional simulator on
-    a generating structure built independently of the evaluation structure
-    (its own seed, m_gen conditioning points, blocks of at most gen_max_bs
-    points so that every joint set fits the simulator).  Returns y (device,
-    original point order)."""
-    n, d = X.shape
-    G = sbv.sbv_build_blocks(X, None, np.exp(theta[:d]), max(1, n // w["gen_bs_mean"]), w["m_gen"],
-                             method=sbv.SBV_KMEANS, lloyd_iters=1, min_bs=0, max_bs=w["gen_max_bs"],
-                             seed=w["seed"] + 7919)
-    th = torch.tensor(theta, dtype=torch.float64, device=dev)
-    xi_d = torch.tensor(xi, dtype=torch.float64, device=dev)
-    y = torch.empty(n, dtype=torch.float64, device=dev)
-    sbv.sbv_sample_dev(G, th, two_nu, xi_d, y)
-    torch.cuda.synchronize()
-    G.free()
-    return y
-
-
 def small_leg(sbv, torch, dev, stream, steps=100):
     """The n = 20,000, d = 10, Matern-5/2, tau^2 = 1e-6, 1,000-block, m = 60
     workload at its true theta: FP64 evaluations per second (structure built
     on the GPU, observations from the simulator)."""
-    from paper_2504_12004_amd import synth
+    from paper_2504_12004_amd import synth, workloads
     w = synth.dataset("small_fp64")
     X, theta, xi = w["X"], w["theta"], w["xi"]
     d = X.shape[1]
     B = sbv.sbv_build_blocks(X, None, np.exp(theta[:d]), w["K"], w["m"], method=sbv.SBV_KMEANS,
                              lloyd_iters=w["lloyd_iters"], seed=w["seed"])
-    y = simulate(sbv, torch, dev, X, theta, xi, w["two_nu"], w)
+    y = workloads.simulate(sbv, torch, dev, X, theta, xi, w["two_nu"], w)
     sbv.sbv_blocks_set_y_dev(B, y)
     th = torch.tensor(theta, dtype=torch.float64, device=dev)
     out = torch.empty(steps + 3, dtype=torch.float64, device=dev)

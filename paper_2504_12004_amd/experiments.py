@@ -1,5 +1,6 @@
 """Larger measurements beyond the benchmark's default run.
 
+    python -m paper_2504_12004_amd.experiments c2fits --out results/c2fits.json
     python -m paper_2504_12004_amd.experiments c3 --out results/c3.json
     python -m paper_2504_12004_amd.experiments c4 --out results/c4.json
     python -m paper_2504_12004_amd.experiments c5 --out results/c5.json
@@ -122,121 +123,94 @@ def c4(out_path, reps=3, fits=True):
     log(f"wrote {out_path}")
 
 
-def _prior(g, d):
-    """Parameter prior of the warm-start study: beta_k ~ logU[0.05, 3],
-    sigma^2 ~ logU[0.5, 2], tau^2 ~ logU[1e-6, 1e-2], nu = 5/2."""
-    from paper_2504_12004_amd import synth
-    beta = synth.log_uniform(g, 0.05, 3.0, d)
-    return synth.theta_vector(beta, synth.log_uniform(g, 0.5, 2.0), synth.log_uniform(g, 1e-6, 1e-2))
-
-
-def c5(out_path, n_train=4096, n_val=512, n_app=2_000_000, epochs=200, nm_evals=500):
-    """Learned warm start.  Training: n_train datasets of n = 2e4 points in
-    [0,1]^10, theta from the prior, y from the conditional simulator (1000
-    k-means blocks, m_gen = 100); 64 summary features each; the 64-256-256-256-12
-    GELU network trained with Adam (lr 1e-3, batch 256) on all but n_val sets.
-    Application: a fresh dataset of n_app points (theta* from the prior, y from
-    the simulator on an independent structure with m_gen = 200); the network
-    predicts theta from its features; one evaluation structure (m = 400,
-    blocks of 5..60 points, built at the predicted ranges) is shared by every
-    fit: Nelder-Mead FP64 and FP32 and L-BFGS FP64 and FP32 from the cold start
-    (beta_k = 1, sigma^2 = var(y), tau^2 = 1e-3 var(y)), and L-BFGS FP32 from
-    the network's prediction; FP32 fits end with an FP64 polish and every
-    optimum is judged by one FP64 evaluation."""
+def c5(out_path, n_train=4096, n_val=512, n_app=20_000_000, epochs=200, nm_evals=100, stage="all",
+       mlp_path=None, legs=None):
+    """Learned warm start (paper_2504_12004_amd/warmstart.py).  Training:
+    n_train datasets of n = 2e4 points in [0,1]^10, theta from the prior,
+    observations from the simulator (1000 k-means blocks, m_gen = 100); 64
+    summary statistics each; the 64-256-256-256-12 GELU network trained with
+    Adam (lr 1e-3, batch 256) on all but n_val sets, early stopping.
+    Application: a fresh dataset of n_app = 2e7 points (theta* from the prior,
+    observations from the simulator on an independent generating structure,
+    m_gen = 250 with blocks of at most 22 points); the warm start is the
+    network's prediction with the nugget from the likelihood profile on a
+    2e4-point subsample; one evaluation structure (m = 400, blocks of 5..60
+    points, built at the warm start's ranges) is shared by every fit:
+    FP32 L-BFGS with an FP64 polish from the warm and from the cold start,
+    FP64 L-BFGS from the cold start, and plain FP64 Nelder-Mead from the cold
+    start with an evaluation cap (nm_evals); every optimum is judged by one
+    FP64 evaluation.  stage = "train" stops after saving the network
+    (mlp_path), stage = "apply" loads it; legs selects fits by name."""
     import torch
     torch.cuda.init()
-    from paper_2504_12004_amd import sbv, synth
-    d, nt_pts, two_nu = 10, 20000, 5
-    g = np.random.default_rng(5)
-    feats = np.empty((n_train, 4 + 5 * (d + 2)), np.float32)
-    targ = np.empty((n_train, d + 2), np.float32)
-    t0 = time.perf_counter()
-    for j in range(n_train):
-        X = g.random((nt_pts, d))
-        th = _prior(g, d)
-        xi = g.standard_normal(nt_pts)
-        Bg = sbv.sbv_build_blocks(X, None, np.exp(th[:d]), 1000, 100, method=sbv.SBV_KMEANS, lloyd_iters=1,
-                                  seed=1000003 + j)
-        y = sbv.sbv_sample(Bg, th, two_nu, xi)
-        Bg.free()
-        feats[j] = sbv.sbv_features(X, y, nt_pts, seed=j)
-        targ[j] = th
-        if (j + 1) % 256 == 0:
-            log(f"training sets: {j + 1}/{n_train} ({time.perf_counter() - t0:.0f} s)")
-    n_val = min(n_val, n_train // 8)
-    res = {"training_sets": n_train, "validation_sets": n_val, "data_seconds": time.perf_counter() - t0}
-    ntr = n_train - n_val
-    mlp = sbv.sbv_mlp_create(feats.shape[1], 256, 3, d + 2, seed=5)
-    t0 = time.perf_counter()
-    # rounds of 10 epochs (Adam's state carries over); keep the parameters with
-    # the lowest validation error (early stopping)
-    best, best_p, best_ep, loss = np.inf, None, 0, None
-    for ep in range(10, epochs + 1, 10):
-        loss = sbv.sbv_mlp_train(mlp, feats[:ntr], targ[:ntr], 10, batch=256, lr=1e-3, seed=5 + ep)
-        err = float(np.mean((sbv.sbv_mlp_predict(mlp, feats[ntr:]) - targ[ntr:]) ** 2))
-        if err < best:
-            best, best_p, best_ep = err, sbv.sbv_mlp_get_params(mlp), ep
-    sbv.sbv_mlp_set_params(mlp, best_p)
-    res["train_seconds"] = time.perf_counter() - t0
-    res["final_train_loss_standardised"] = loss
-    res["epochs_kept"] = best_ep
-    pred = sbv.sbv_mlp_predict(mlp, feats[ntr:])
-    rm = np.sqrt(np.mean((pred - targ[ntr:]) ** 2, axis=0))
-    rb = np.sqrt(np.mean((targ[:ntr].mean(axis=0) - targ[ntr:]) ** 2, axis=0))
-    res["val_rmse_log_theta"] = rm.tolist()
-    res["val_rmse_mean_predictor"] = rb.tolist()
-    log(f"network: kept epoch {best_ep}, validation RMSE (log theta) mean {rm.mean():.3f} "
-        f"vs mean predictor {rb.mean():.3f}")
-    sbv.sbv_mlp_save(mlp, out_path + ".mlp")
-
-    # application
+    from paper_2504_12004_amd import sbv, workloads
+    from paper_2504_12004_amd import warmstart as W
+    d, two_nu = 10, 5
+    res = {}
+    mlp_path = mlp_path or out_path + ".mlp"
+    if stage in ("all", "train"):
+        t0 = time.perf_counter()
+        F, T = W.training_sets(n_train, 20000, d, seed=5, blocks=1000, m_gen=100, log=log)
+        res["training_sets"], res["data_seconds"] = n_train, time.perf_counter() - t0
+        t0 = time.perf_counter()
+        mlp, ep = W.train(F, T, n_val, epochs=epochs)
+        res["train_seconds"], res["epochs_kept"] = time.perf_counter() - t0, ep
+        ntr = n_train - n_val
+        pred = sbv.sbv_mlp_predict(mlp, F[ntr:])
+        res["val_rmse_log_theta"] = np.sqrt(np.mean((pred - T[ntr:]) ** 2, axis=0)).tolist()
+        res["val_rmse_mean_predictor"] = np.sqrt(np.mean((T[:ntr].mean(0) - T[ntr:]) ** 2, axis=0)).tolist()
+        log(f"network: epoch {ep}, validation RMSE {np.round(res['val_rmse_log_theta'], 2)} vs mean predictor "
+            f"{np.round(res['val_rmse_mean_predictor'], 2)}")
+        sbv.sbv_mlp_save(mlp, mlp_path)
+        if stage == "train":
+            with open(out_path, "w") as f:
+                json.dump(res, f, indent=1)
+            return
+    else:
+        mlp = sbv.sbv_mlp_load(mlp_path, d + 2)
+    dev = torch.device("cuda:0")
     ga = np.random.default_rng(6)
     X = ga.random((n_app, d))
-    th_true = _prior(ga, d)
+    th_true = W.prior(ga, d)
     xi = ga.standard_normal(n_app)
-    K = n_app // 20
-    Bg = sbv.sbv_build_blocks(X, None, np.exp(th_true[:d]), K, 200, method=sbv.SBV_KMEANS, lloyd_iters=1,
-                              min_bs=5, max_bs=60, seed=7)
-    y = sbv.sbv_sample(Bg, th_true, two_nu, xi)
-    Bg.free()
-    f_app = sbv.sbv_features(X, y, nt_pts, seed=11)
-    th_warm = sbv.sbv_mlp_predict(mlp, f_app[None, :].astype(np.float32))[0].astype(np.float64)
+    t0 = time.perf_counter()
+    wgen = dict(seed=6, m_gen=250, gen_bs_mean=10, gen_max_bs=22)
+    y = workloads.simulate(sbv, torch, dev, X, th_true, xi, two_nu, wgen).cpu().numpy()
+    log(f"application observations simulated in {time.perf_counter() - t0:.0f} s")
+    t0 = time.perf_counter()
+    th_warm, th_net = W.predict(mlp, X, y, two_nu, sub_n=20000, seed=11)
+    t_warm = time.perf_counter() - t0
     mlp.free()
-    var_y = float(np.var(y))
-    th_cold = np.r_[np.zeros(d), np.log(var_y), np.log(1e-3 * var_y)]
-    res["application"] = {"n": n_app, "K": K, "m": 400, "theta_true": th_true.tolist(),
-                          "theta_warm": th_warm.tolist(), "theta_cold": th_cold.tolist(),
-                          "warm_abs_err": np.abs(th_warm - th_true).tolist(),
-                          "cold_abs_err": np.abs(th_cold - th_true).tolist()}
+    th_cold = W.cold_start(y, d)
+    K = n_app // 20
+    app = {"n": n_app, "K": K, "m": 400, "theta_true": th_true.tolist(), "theta_net": th_net.tolist(),
+           "theta_warm": th_warm.tolist(), "theta_cold": th_cold.tolist(), "warm_start_seconds": t_warm,
+           "warm_abs_err": np.abs(th_warm - th_true).tolist(), "cold_abs_err": np.abs(th_cold - th_true).tolist()}
     t0 = time.perf_counter()
     B = sbv.sbv_build_blocks(X, y, np.exp(th_warm[:d]), K, 400, method=sbv.SBV_KMEANS, lloyd_iters=2, min_bs=5,
                              max_bs=60, seed=8)
-    res["application"]["build_seconds"] = time.perf_counter() - t0
-    log(f"application structure: n = {n_app}, K = {B.K}, built in {res['application']['build_seconds']:.1f} s")
-    res["application"]["loglik_fp64_at_true"] = float(sbv.sbv_loglik(B, th_true, two_nu)[0])
-    ckpt = out_path + ".ckpt"
-    legs = [("nm_fp64_cold", sbv.SBV_NELDER_MEAD, sbv.SBV_FP64, False, th_cold, nm_evals),
-            ("nm_fp32_cold_polish64", sbv.SBV_NELDER_MEAD, sbv.SBV_FP32, True, th_cold, nm_evals),
-            ("lbfgs_fp64_cold", sbv.SBV_LBFGS, sbv.SBV_FP64, False, th_cold, 400),
-            ("lbfgs_fp32_cold_polish64", sbv.SBV_LBFGS, sbv.SBV_FP32, True, th_cold, 400),
-            ("lbfgs_fp32_warm_polish64", sbv.SBV_LBFGS, sbv.SBV_FP32, True, th_warm, 400)]
+    app["build_seconds"] = time.perf_counter() - t0
+    log(f"application structure: n = {n_app}, K = {B.K}, built in {app['build_seconds']:.1f} s")
+    del X
+    for prec in (sbv.SBV_FP32, sbv.SBV_FP64):
+        sbv.sbv_autotune([B], th_warm, two_nu, prec, reps=1)
+    app["loglik_fp64_at_true"] = float(sbv.sbv_loglik(B, th_true, two_nu)[0])
+    all_legs = [("lbfgs_fp32_warm_polish64", sbv.SBV_LBFGS, sbv.SBV_FP32, True, th_warm, 400),
+                ("lbfgs_fp32_cold_polish64", sbv.SBV_LBFGS, sbv.SBV_FP32, True, th_cold, 400),
+                ("lbfgs_fp64_cold", sbv.SBV_LBFGS, sbv.SBV_FP64, False, th_cold, 400),
+                ("nm_fp64_cold", sbv.SBV_NELDER_MEAD, sbv.SBV_FP64, False, th_cold, nm_evals)]
     fits = {}
-    for name, opt, prec, polish, x0, me in legs:
-        if os.path.exists(ckpt):
-            os.remove(ckpt)
+    for name, opt, prec, polish, x0, me in all_legs:
+        if legs and name not in legs:
+            continue
         o = sbv.make_fit_opts(optimizer=opt, prec=prec, fp64_polish=polish, max_evals=me, ftol=1e-12,
-                              gtol=1e-6 * n_app, checkpoint_path=ckpt)
+                              gtol=1e-6 * n_app)
         log(f"fit {name}")
         th, l64, ne, sec, conv = sbv.sbv_fit(B, x0, two_nu, o)
         fits[name] = {"seconds": sec, "evals": ne, "loglik_fp64": l64, "converged": conv, "theta": th.tolist()}
         log(f"fit {name}: {sec:.1f} s, {ne} evals, l64 {l64:.6f}, converged {conv}")
-    if os.path.exists(ckpt):
-        os.remove(ckpt)
-    base = fits["nm_fp64_cold"]["loglik_fp64"]
-    for k in fits:
-        fits[k]["rel_gap_vs_nm_fp64"] = (fits[k]["loglik_fp64"] - base) / abs(base)
-        fits[k]["gap_nats_vs_nm_fp64"] = fits[k]["loglik_fp64"] - base
-    res["application"]["fits"] = fits
+    app["fits"] = fits
+    res["application"] = app
     B.free()
     with open(out_path, "w") as f:
         json.dump(res, f, indent=1)
@@ -329,14 +303,72 @@ def c3(out_path, reps=3):
     log(f"wrote {out_path}")
 
 
+def c2fits(out_path, nm_evals=20000):
+    """MLE fits on the n = 1e6, m = 200 benchmark workload (observations from
+    the simulator on an independent generating structure, as in the
+    benchmark), all from the cold start (beta_k = 1, sigma^2 = var(y),
+    tau^2 = 1e-3 var(y)) on one shared structure built at the generating
+    ranges: plain FP64 Nelder-Mead run to convergence (ftol 1e-10, up to
+    nm_evals evaluations), FP32 Nelder-Mead with an FP64 polish, FP64 L-BFGS,
+    FP32 L-BFGS with an FP64 polish.  Every optimum is judged by one FP64
+    evaluation; the report gives wall times, evaluations, the FP64
+    log-likelihood gap to the converged Nelder-Mead (nats and relative), and
+    the distance of theta_hat from the generating theta."""
+    import torch
+    torch.cuda.init()
+    from paper_2504_12004_amd import sbv, synth, workloads
+    w = synth.dataset("uneven_1m")
+    X, th_true, xi = w["X"], w["theta"], w["xi"]
+    n, d = X.shape
+    dev = torch.device("cuda:0")
+    B = sbv.sbv_build_blocks(X, None, np.exp(th_true[:d]), w["K"], w["m"], method=sbv.SBV_KMEANS,
+                             lloyd_iters=w["lloyd_iters"], min_bs=w["min_bs"], max_bs=w["max_bs"], seed=w["seed"])
+    y = workloads.simulate(sbv, torch, dev, X, th_true, xi, w["two_nu"], w)
+    sbv.sbv_blocks_set_y_dev(B, y)
+    torch.cuda.synchronize()
+    for prec in (sbv.SBV_FP64, sbv.SBV_FP32):
+        sbv.sbv_autotune([B], th_true, w["two_nu"], prec, reps=3)
+    var_y = float(torch.var(y).item())
+    x0 = np.r_[np.zeros(d), np.log(var_y), np.log(1e-3 * var_y)]
+    res = {"n": n, "K": B.K, "m": w["m"], "theta_true": th_true.tolist(), "theta_cold": x0.tolist(),
+           "loglik_fp64_at_true": float(sbv.sbv_loglik(B, th_true, w["two_nu"])[0])}
+    legs = [("nm_fp64", sbv.SBV_NELDER_MEAD, sbv.SBV_FP64, False, nm_evals, 1e-10),
+            ("nm_fp32_polish64", sbv.SBV_NELDER_MEAD, sbv.SBV_FP32, True, nm_evals, 1e-10),
+            ("lbfgs_fp64", sbv.SBV_LBFGS, sbv.SBV_FP64, False, 1000, 1e-12),
+            ("lbfgs_fp32_polish64", sbv.SBV_LBFGS, sbv.SBV_FP32, True, 1000, 1e-12)]
+    fits = {}
+    for name, opt, prec, polish, me, ftol in legs:
+        o = sbv.make_fit_opts(optimizer=opt, prec=prec, fp64_polish=polish, max_evals=me, ftol=ftol, gtol=1e-3,
+                              init_step=0.5)
+        log(f"fit {name}")
+        th, l64, ne, sec, conv = sbv.sbv_fit(B, x0, w["two_nu"], o)
+        fits[name] = {"seconds": sec, "evals": ne, "loglik_fp64": l64, "converged": conv, "theta": th.tolist(),
+                      "max_abs_log_theta_err": float(np.max(np.abs(th - th_true)))}
+        log(f"fit {name}: {sec:.2f} s, {ne} evals, l64 {l64:.6f}, converged {conv}, "
+            f"max |theta - theta*| {fits[name]['max_abs_log_theta_err']:.3f}")
+    base = fits["nm_fp64"]["loglik_fp64"]
+    for k in fits:
+        fits[k]["gap_nats_vs_nm_fp64"] = fits[k]["loglik_fp64"] - base
+        fits[k]["rel_gap_vs_nm_fp64"] = (fits[k]["loglik_fp64"] - base) / abs(base)
+        fits[k]["speedup_vs_nm_fp64"] = fits["nm_fp64"]["seconds"] / fits[k]["seconds"]
+    res["fits"] = fits
+    B.free()
+    with open(out_path, "w") as f:
+        json.dump(res, f, indent=1)
+    log(f"wrote {out_path}")
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("what", choices=["c3", "c4", "c5", "accuracy"])
+    ap.add_argument("what", choices=["c2fits", "c3", "c4", "c5", "accuracy"])
     ap.add_argument("--out", required=True)
     ap.add_argument("--reps", type=int, default=3)
     ap.add_argument("--no-fits", action="store_true")
     ap.add_argument("--train-sets", type=int, default=4096)
-    ap.add_argument("--app-n", type=int, default=2_000_000)
+    ap.add_argument("--app-n", type=int, default=20_000_000)
+    ap.add_argument("--stage", choices=["all", "train", "apply"], default="all")
+    ap.add_argument("--mlp", default=None)
+    ap.add_argument("--legs", default=None, help="comma-separated fit names (C5)")
     a = ap.parse_args()
     os.makedirs(os.path.dirname(os.path.abspath(a.out)), exist_ok=True)
     if a.what == "c4":
@@ -344,7 +376,10 @@ def main():
     elif a.what == "c3":
         c3(a.out, a.reps)
     elif a.what == "c5":
-        c5(a.out, n_train=a.train_sets, n_app=a.app_n)
+        c5(a.out, n_train=a.train_sets, n_app=a.app_n, stage=a.stage, mlp_path=a.mlp,
+           legs=a.legs.split(",") if a.legs else None)
+    elif a.what == "c2fits":
+        c2fits(a.out)
     elif a.what == "accuracy":
         from . import accuracy
         accuracy.study(a.out)
