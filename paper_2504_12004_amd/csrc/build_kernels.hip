@@ -235,8 +235,9 @@ __global__ __launch_bounds__(256) void k_knn_coarse(const double* __restrict__ c
 // Fine step: one wave per query; the points of its candidate blocks within
 // lambda_q of the centroid go through the same candidate buffer and sort as the
 // brute-force search.  The result is exact when at least m_q points lie within
-// lambda_q (every point that close was examined); otherwise, or when the
-// candidate list overflowed, status[i] = 1 and the query is retried.
+// lambda_q (every point that close was examined); otherwise status[i] = 1 and
+// the query is retried with a larger threshold, or status[i] = 2 when its
+// candidate list overflowed (it goes to the brute-force search).
 __global__ __launch_bounds__(kKnnWaves * 64) void k_knn_fine(const double* __restrict__ Z, int d,
                                                              const double* __restrict__ cen,
                                                              const int32_t* __restrict__ bptr,
@@ -253,8 +254,8 @@ __global__ __launch_bounds__(kKnnWaves * 64) void k_knn_fine(const double* __res
   const int q = qlist[i];
   const int mi = (int)(nn_ptr[q + 1] - nn_ptr[q]);
   const int nc = ccount[i];
-  if (nc > cap) {
-    if (lane == 0) status[i] = 1;
+  if (nc > cap) {  // too many candidate blocks: a larger threshold would not help
+    if (lane == 0) status[i] = 2;
     return;
   }
   double c[kMaxDim];

@@ -18,6 +18,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <numeric>
 #include <string>
@@ -41,6 +43,20 @@ sbv_status sbv_internal_make_handle(const double* X, const double* y, int64_t n,
 namespace {
 
 using namespace sbv;
+
+// Progress lines on stderr when the environment variable SBV_PROGRESS is set
+// (builds of 1e7+ points take minutes).
+void progress(const char* what, double a = -1.0, double b = -1.0) {
+  static const bool on = std::getenv("SBV_PROGRESS") != nullptr;
+  if (!on) return;
+  if (b >= 0.0)
+    std::fprintf(stderr, "[build] %s %.0f / %.0f\n", what, a, b);
+  else if (a >= 0.0)
+    std::fprintf(stderr, "[build] %s %.0f\n", what, a);
+  else
+    std::fprintf(stderr, "[build] %s\n", what);
+  std::fflush(stderr);
+}
 
 struct Splitmix {
   uint64_t s;
@@ -140,6 +156,7 @@ sbv_status cluster_points(const std::vector<double>& Z, int64_t n, int d, int64_
   };
   sbv_status st = assign();
   if (st) return st;
+  progress("anchor assignment done, clusters", (double)K);
   for (int it = 0; it < lloyd; ++it) {
     cluster_means(Z, n, d, lab, K, C, cnt);
     for (int64_t c = 0; c < K; ++c) {
@@ -164,6 +181,7 @@ sbv_status cluster_points(const std::vector<double>& Z, int64_t n, int d, int64_
     prev = lab;
     st = assign();
     if (st) return st;
+    progress("lloyd pass", (double)(it + 1), (double)lloyd);
     if (prev == lab) break;
   }
   // 5. size bounds
@@ -255,9 +273,10 @@ sbv_status cluster_points(const std::vector<double>& Z, int64_t n, int d, int64_
 // V the volume of the scaled inputs' bounding box.  Candidate blocks pass
 // ||c_q - c_j|| <= lambda_q + radius_j, candidate points ||z - c_q|| <= lambda_q,
 // and the answer is exact once at least m_q points lie within lambda_q.
-// Queries that fall short (or overflow their candidate list) retry with
-// 2 lambda_q, four times at most; what remains, and queries with fewer than
-// 8 m_q earlier points, go to the brute-force search.
+// Queries that fall short retry with lambda_q 4^(1/d) (a ball expected to
+// hold four times as many points), four times at most; what
+// remains, queries whose candidate list overflows, and queries with fewer
+// than 8 m_q earlier points go to the brute-force search.
 sbv_status filtered_knn(const std::vector<double>& Zo, const std::vector<double>& cen, const std::vector<int32_t>& bp,
                         const std::vector<int64_t>& nptr, int64_t n, int d, int64_t K, double alpha, const double* dZo,
                         const double* dcen, const int32_t* dbp, const int64_t* dnp, int32_t* dpos) {
@@ -303,7 +322,9 @@ sbv_status filtered_knn(const std::vector<double>& Zo, const std::vector<double>
   BTRY(dst.alloc(kBatch));
   for (int attempt = 0; attempt < 5 && !pending.empty(); ++attempt) {
     std::vector<int32_t> failed;
+    progress("filtered neighbour search, pass / queries", (double)attempt, (double)pending.size());
     for (size_t b0 = 0; b0 < pending.size(); b0 += kBatch) {
+      if ((b0 / kBatch) % 16 == 15) progress("  queries done", (double)b0, (double)pending.size());
       const int nb = (int)std::min<size_t>(kBatch, pending.size() - b0);
       std::vector<double> lb(nb);
       for (int i = 0; i < nb; ++i) lb[i] = lam[pending[b0 + i]];
@@ -313,10 +334,13 @@ sbv_status filtered_knn(const std::vector<double>& Zo, const std::vector<double>
       BTRY(launch_knn_fine(dZo, d, dcen, dbp, dq.p, nb, dlam.p, kCap, dcand.p, dcnt.p, dnp, dpos, dst.p, nullptr));
       std::vector<int32_t> sb(nb);
       BTRY(hipMemcpy(sb.data(), dst.p, sizeof(int32_t) * nb, hipMemcpyDeviceToHost));
-      for (int i = 0; i < nb; ++i)
-        if (sb[i]) failed.push_back(pending[b0 + i]);
+      for (int i = 0; i < nb; ++i) {
+        if (sb[i] == 1) failed.push_back(pending[b0 + i]);
+        if (sb[i] == 2) brute.push_back(pending[b0 + i]);
+      }
     }
-    for (int32_t q : failed) lam[q] *= 2.0;
+    const double grow = std::pow(4.0, 1.0 / d);  // four times the expected points inside
+    for (int32_t q : failed) lam[q] *= grow;
     pending.swap(failed);
   }
   brute.insert(brute.end(), pending.begin(), pending.end());
@@ -400,6 +424,7 @@ extern "C" sbv_status sbv_build_blocks(const double* X, const double* y, int64_t
     }
     K = koff;
   }
+  progress("clusters after size bounds", (double)K);
   // 6. random block order
   std::vector<int64_t> order(K), rank_of(K);
   std::iota(order.begin(), order.end(), 0);
@@ -458,6 +483,7 @@ extern "C" sbv_status sbv_build_blocks(const double* X, const double* y, int64_t
   }
   std::vector<int64_t> nidx(std::max<int64_t>(nnz, 1));
   for (int64_t t = 0; t < nnz; ++t) nidx[t] = pts[npos[t]];
+  progress("neighbours done");
   // 9. pack
   st = sbv_internal_make_handle(X, y, n, d, K, bptr.data(), pts.data(), nptr.data(), nidx.data(), out);
   if (st == SBV_OK) sbv_internal_set_build(*out, beta_build, n_blocks, m, o);

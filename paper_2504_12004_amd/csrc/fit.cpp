@@ -16,6 +16,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <fstream>
 #include <sstream>
@@ -29,6 +30,13 @@ bool sbv_internal_was_built(sbv_blocks h);
 sbv_status sbv_internal_rebuild(sbv_blocks h, const double* beta_build);
 
 namespace {
+
+// Progress lines on stderr when the environment variable SBV_PROGRESS is set
+// (long fits at large n report every iteration).
+bool progress_on() {
+  static const bool on = std::getenv("SBV_PROGRESS") != nullptr;
+  return on;
+}
 
 struct Objective {
   sbv_objective fn;
@@ -190,6 +198,9 @@ sbv_status nelder_mead(Objective& obj, std::vector<double>& x, const sbv_fit_opt
     st.evals = obj.evals;
     save_state(o.checkpoint_path, st);
     ++st.iter;
+    if (progress_on() && st.iter % 25 == 0)
+      std::fprintf(stderr, "[fit] nelder-mead iteration %lld, %lld evaluations, f %.10g\n", (long long)st.iter,
+                   (long long)obj.evals, F[0]);
     const double spread = F[n] - F[0];
     if (std::isfinite(F[n]) && spread <= o.ftol * (std::fabs(F[0]) + 1e-300)) {
       converged = true;
@@ -380,6 +391,9 @@ sbv_status lbfgs(Objective& obj, std::vector<double>& x, const sbv_fit_opts& o, 
     ++st.iter;
     double gmax = 0.0;
     for (double v : g) gmax = std::max(gmax, std::fabs(v));
+    if (progress_on())
+      std::fprintf(stderr, "[fit] l-bfgs iteration %lld, %lld evaluations, f %.12g, max |g| %.3g\n",
+                   (long long)st.iter, (long long)obj.evals, f, gmax);
     if (gmax <= o.gtol) {
       converged = true;
       break;
