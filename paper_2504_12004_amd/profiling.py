@@ -16,6 +16,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import sqlite3
 import subprocess
 import sys
@@ -257,8 +258,13 @@ def summarize_large(out, write_dir):
                 if line.startswith("{"):
                     bench_line = json.loads(line)
     big = bench_line["extra"]["m400_5m"] if bench_line else None
-    # kernels of the large path, FP64 forward (the prefix kernel and the
-    # register kernel in large-block mode: last template flag true)
+    # kernels of the large path in FP64: the prefix-elimination kernel and the
+    # register kernel in large-block mode (last template flag true), forward
+    # (GRAD false) or gradient (GRAD true).  A prefix launch belongs to the
+    # register launch that follows it.  FP32 evaluations also launch the FP64
+    # pair over their fallback list, which is empty unless a block lost
+    # positive definiteness: such launches end within microseconds and are
+    # counted apart.
     rows = list(tr.execute("select name, duration from kernels order by dispatch_id"))
 
     def kind(name):
@@ -266,11 +272,28 @@ def summarize_large(out, write_dir):
             return "prefix"
         if "k_block_loglik<double, 17, 8, false, false, false, true>" in name:
             return "trailing"
+        if "k_block_loglik<double, 17, 8, true, false, false, true>" in name:
+            return "trailing_grad"
         return None
-    per = {}
+    empty_ns = 50e3
+    per, n_empty, pending = {}, {}, []
     for name, dur in rows:
         k = kind(name)
-        if k:
+        if k == "prefix":
+            pending.append(dur)
+            continue
+        if k is None:
+            continue
+        pk = "prefix" if k == "trailing" else "prefix_grad"
+        for dp in pending:
+            if dp < empty_ns:
+                n_empty[pk] = n_empty.get(pk, 0) + 1
+            else:
+                per.setdefault(pk, []).append(dp)
+        pending = []
+        if dur < empty_ns:
+            n_empty[k] = n_empty.get(k, 0) + 1
+        else:
             per.setdefault(k, []).append(dur)
     fetch = _counter(_db(f"{out}/fetch"), "FETCH_SIZE")
     write = _counter(_db(f"{out}/write"), "WRITE_SIZE")
@@ -282,26 +305,44 @@ def summarize_large(out, write_dir):
 
     def bytes_of(counter, scale, k):
         v = [x for (name, _), vals in counter.items() if kind(name) == k for x in vals]
-        return (sum(v) * 1024 * scale, len(v)) if v else (None, 0)
+        return sum(v) * 1024 * scale if v else None
+    m = re.search(r"--large-steps (\d+)", cmds.get("trace", ""))
+    evals = int(m.group(1)) + 1 if m else None
     L = ["# Large-set path on m400_5m (n = 5e6, d = 10, K = 2.5e5, m = 400, FP64)\n",
          "Made by `python -m paper_2504_12004_amd.profiling run --workload m400_5m` then "
          "`... summarize --workload m400_5m`, which ran:\n"]
     for k in ("trace", "fetch", "write", "copy_fetch", "copy_write"):
         if k in cmds:
             L.append(f"- {k}: `{cmds[k]}`")
-    L += ["", "The FP64 evaluations of the leg (1 warm-up + 2 timed, plus the gradient runs that also", 
-          "launch the prefix kernel) are all in the trace; the table lists every FP64 forward launch.", "",
-          "| kernel | launches | total ms | avg ms | FETCH GB | WRITE GB |", "|---|---|---|---|---|---|"]
-    res = {"kernel_source_hash": kernel_source_hash()}
-    for k, label in (("prefix", "k_block_prefix<double, 8>"),
-                     ("trailing", "k_block_loglik<double, 17, 8, ..., large-block mode>")):
+    L += ["", f"The trace holds {evals} FP64 forward evaluations (1 warm-up + the timed ones) and as many",
+          "gradient evaluations, each of them one window after another of prefix + register launches.",
+          f"FP32 evaluations launch the FP64 pair over their (empty) fallback lists: launches under "
+          f"{empty_ns / 1e3:.0f} us", "are counted apart and left out of the averages. The counter runs "
+          "repeat the same command; their bytes", "(scaled by the copy-kernel calibration) are split over "
+          "the non-empty launches, prefix bytes over", "forward and gradient prefix launches alike (the "
+          "prefix kernel does the same work in both).", "",
+          "| kernel | launches | empty | avg ms | ms per evaluation | FETCH GB/launch | WRITE GB/launch |",
+          "|---|---|---|---|---|---|---|"]
+    res = {"kernel_source_hash": kernel_source_hash(), "evaluations": evals}
+    n_pref = len(per.get("prefix", [])) + len(per.get("prefix_grad", []))
+    for k, label in (("prefix", "k_block_prefix<double, 8> (forward)"),
+                     ("prefix_grad", "k_block_prefix<double, 8> (gradient)"),
+                     ("trailing", "k_block_loglik<double, 17, 8, forward, large-block mode>"),
+                     ("trailing_grad", "k_block_loglik<double, 17, 8, gradient, large-block mode>")):
         d = per.get(k, [])
-        fb, nf = bytes_of(fetch, f_scale, k)
-        wb, nw = bytes_of(write, w_scale, k)
-        L.append(f"| `{label}` | {len(d)} | {sum(d) / 1e6:.1f} | {sum(d) / max(len(d), 1) / 1e6:.3f} | "
-                 f"{(fb or 0) / 1e9:.2f} ({nf} launches) | {(wb or 0) / 1e9:.2f} ({nw} launches) |")
-        res[k] = {"launches": len(d), "total_ms": sum(d) / 1e6, "fetch_bytes": fb, "write_bytes": wb,
-                  "counter_launches": nf}
+        ck_ = "prefix" if k.startswith("prefix") else k
+        nl = n_pref if ck_ == "prefix" else len(d)
+        fb, wb = bytes_of(fetch, f_scale, ck_), bytes_of(write, w_scale, ck_)
+        fpl = fb / nl if fb and nl else None
+        wpl = wb / nl if wb and nl else None
+        avg = sum(d) / max(len(d), 1) / 1e6
+        per_eval = sum(d) / 1e6 / evals if evals else None
+        L.append(f"| `{label}` | {len(d)} | {n_empty.get(k, 0)} | {avg:.3f} | "
+                 f"{'%.1f' % per_eval if per_eval is not None else '-'} | "
+                 f"{'%.3f' % (fpl / 1e9) if fpl else '-'} | {'%.3f' % (wpl / 1e9) if wpl else '-'} |")
+        res[k] = {"launches": len(d), "empty_launches": n_empty.get(k, 0), "total_ms": sum(d) / 1e6,
+                  "avg_ms": avg, "ms_per_eval": per_eval, "fetch_bytes_per_launch": fpl,
+                  "write_bytes_per_launch": wpl}
     if big:
         L += ["", f"- benchmark (same run): FP64 {big['fp64']['ms_per_eval']:.1f} ms per evaluation, "
               f"{big['algorithmic_tflop_per_eval']:.3f} TFLOP algorithmic per evaluation, "
