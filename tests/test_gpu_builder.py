@@ -124,9 +124,10 @@ def test_builder_neighbours_at_full_size(sbv):
 
 def test_filtered_neighbour_search_equals_brute_force(sbv):
     """The filtered search (Alg. 4 with the threshold of Eq.
-    (distancethreashold), conservative candidate test, retries at twice the
-    threshold) gives exactly the brute-force structure, for the default
-    expansion factor and for one so small that most queries need retries."""
+    (distancethreashold), conservative candidate test, retries with the
+    threshold grown by 4^(1/d), brute force for what is left) gives exactly
+    the brute-force structure, for the default expansion factor and for one
+    so small that most queries need retries."""
     rng = np.random.default_rng(41)
     X = rng.random((20000, 10))
     bb = np.exp(rng.uniform(np.log(0.1), np.log(2.0), 10))
