@@ -216,9 +216,12 @@ __device__ __forceinline__ float shfl_d(float v, int src) { return __shfl(v, src
 // Lane j of every 16-lane row broadcast to its row (DPP row_newbcast, j a
 // constant after unrolling), and row gj broadcast to all four rows
 // (v_permlane16_swap then v_permlane32_swap).  Both checked on the device.
+// Every lane of a row broadcast has a valid source, so the old value is never
+// kept; bound_ctrl with old = 0 says so and lets the compiler write the
+// broadcast into a fresh register instead of copying the source first.
 template <int J>
 __device__ __forceinline__ unsigned nb_u(unsigned v) {
-  return (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x150 + J, 0xf, 0xf, false);
+  return (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x150 + J, 0xf, 0xf, true);
 }
 __device__ __forceinline__ unsigned row_lane_u(unsigned v, int j) {
   switch (j) {
@@ -249,7 +252,7 @@ __device__ __forceinline__ unsigned row_all_u(unsigned x, int gj) {
 // FP64: one 64-bit DPP move (v_mov_b64 row_newbcast, checked on the device)
 template <int J>
 __device__ __forceinline__ double nb_d(double v) {
-  return __builtin_amdgcn_update_dpp(v, v, 0x150 + J, 0xf, 0xf, false);
+  return __builtin_amdgcn_update_dpp(0.0, v, 0x150 + J, 0xf, 0xf, true);
 }
 __device__ __forceinline__ double row_lane(double v, int j) {
   switch (j) {
@@ -307,31 +310,42 @@ __device__ __forceinline__ float rows_sum(float v) {
 // (r, g) = (l % 16, l / 16) holds columns c = g + 4q (q = 0..3) of row r.
 // Right-looking pivots; by symmetry of the trailing matrix the column-j
 // entries L[c][j] a lane needs are row j's entries of its own columns, read
-// from lane (j, g).  The same loop eliminates the rows of X = L^{-1} (lane
-// (r, g) holds X[r][g + 4q], starting from the identity) and solves
-// z_k = L_kk^{-1} y_k, so no second pass is needed; -X^T is then published
-// for the column solves.  Lanes r < 16 return the pivot L_rr and z_r; `bad`
-// is raised for a non-positive or non-finite pivot and `low` for a pivot at or
-// below tau * original diagonal (the FP32 fallback test).
+// from lane (j, g).  Every update of step j takes the one multiplier
+// L[r][j] / L[j][j] per row.  The same loop eliminates the rows of W, the
+// inverse X = L^{-1} with its rows not yet divided by their pivots (lane (r, g)
+// holds W[r][g + 4q], starting from the identity): row j of X is W[j] / L[j][j],
+// so its elimination from row r is W[r] -= (L[r][j] / L[j][j]) W[j], and the
+// division of every row by its pivot is left to the end.  Then
+// z_k = L_kk^{-1} y_k = X y_k and -X^T is published for the column solves.
+// Lanes r < 16 return the pivot L_rr and z_r.  Each lane keeps its row's pivot
+// before the square root; after the loop `bad` is raised for a non-positive or
+// non-finite pivot and `low` for a pivot at or below tau * original diagonal
+// (the FP32 fallback test).
 template <typename T, bool SAMPLE = false, class SM>
 __device__ __forceinline__ void factor_diag(SM& sm, T* negM_out, int lane, int k, int nreal, T diag0, T tau,
                                             T& pivot_out, T& z_out, int& bad, int& low, int mi = 0,
                                             T* ysim = nullptr, T* vacc = nullptr) {
-  const int r = lane & 15, g = lane >> 4;
-  T a[4], x[4];
+  // The lane index passes through an empty asm statement, so that the
+  // compiler cannot hoist the lane-against-constant comparisons of the
+  // unrolled steps out of the callers' tile loops: kept live there, they
+  // exhausted the scalar registers and spilled (to vector lanes and scratch).
+  int ln = lane;
+  __asm__ volatile("" : "+v"(ln));
+  const int r = ln & 15, g = ln >> 4;
+  T a[4], w[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int c = g + 4 * q;
     a[q] = sm.diag[r * kDiagLd + c];
-    x[q] = (c == r) ? T(1) : T(0);
+    w[q] = (c == r) ? T(1) : T(0);
   }
   T yr = sm.yv[kTile * k + r];
+  T pv = T(1);  // this lane's row pivot, before the square root
 #pragma unroll
   for (int j = 0; j < 16; ++j) {
     const int gj = j & 3, qj = j >> 2;
     const T piv = rlane(a[qj], j + 16 * gj);
-    if (!(piv > T(0)) || !(piv == piv) || piv > T(3.0e38)) bad = 1;
-    if (piv <= tau * (j < nreal ? diag0 : T(1))) low = 1;
+    pv = (r == j) ? piv : pv;
     const T rs = rsqrt_nr(piv);
     const T sq = piv * rs;
     // A[r][j] of my row and row j of my columns, before this step's update.
@@ -343,32 +357,27 @@ __device__ __forceinline__ void factor_diag(SM& sm, T* negM_out, int lane, int k
 #pragma unroll
     for (int q = 0; q < 4; ++q)
       if (4 * q + 3 > j) ajc[q] = row_lane(a[q], j);
-    const T lrj = (r == j) ? sq : arj * rs;  // L[r][j] (r >= j)
-    const T lrm = (r > j) ? lrj : T(0);      // the same below the pivot, 0 elsewhere
+    const T lrj = (r == j) ? sq : arj * rs;   // L[r][j] (r >= j)
+    const T lrs = (r > j) ? lrj * rs : T(0);  // L[r][j] / L[j][j] below the pivot, 0 elsewhere
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       if (4 * q + 3 < j) continue;
       if (4 * q > j) {
-        a[q] -= lrm * (ajc[q] * rs);
+        a[q] -= lrs * ajc[q];
       } else {
         const int c = g + 4 * q;
-        if (c > j) a[q] = (r > j) ? a[q] - lrj * (ajc[q] * rs) : a[q];
+        if (c > j) a[q] = (r > j) ? a[q] - lrs * ajc[q] : a[q];
         if (c == j) a[q] = (r >= j) ? lrj : a[q];
       }
     }
-    // row j of X is final after scaling, then eliminated from the rows below;
-    // X[j][c] = 0 for c > j, so registers with 4q > j take no part
-    const T srow = (r == j) ? rs : T(1);
+    // W[j][c] = 0 for c > j, so registers with 4q > j take no part
+    T wjc[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q)
-      if (4 * q <= j) x[q] *= srow;
-    T xjc[4];
+      if (4 * q <= j) wjc[q] = row_lane(w[q], j);
 #pragma unroll
     for (int q = 0; q < 4; ++q)
-      if (4 * q <= j) xjc[q] = row_lane(x[q], j);
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-      if (4 * q <= j) x[q] -= lrm * xjc[q];
+      if (4 * q <= j) w[q] -= lrs * wjc[q];
     if (SAMPLE) {
       T zj;
       // conditional simulation: rows of J are solved (w = z), rows of B take
@@ -385,6 +394,13 @@ __device__ __forceinline__ void factor_diag(SM& sm, T* negM_out, int lane, int k
       yr = (r == j) ? zj : (r > j ? yr - lrj * zj : yr);
     }
   }
+  if (__any(!(pv > T(0)) || !(pv == pv) || pv > T(3.0e38))) bad = 1;
+  if (__any(pv <= tau * (r < nreal ? diag0 : T(1)))) low = 1;
+  // rows of X: W[r] / L[r][r]
+  const T rsr = rsqrt_nr(pv);
+  T x[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) x[q] = w[q] * rsr;
   if (SAMPLE && vacc) {
     // conditional variance of the block's rows of this tile: the within-tile
     // part of sum over the block's columns c <= r of L[r][c]^2 (columns of
