@@ -80,7 +80,30 @@ __device__ __forceinline__ float rlane(float v, int l) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
 }
 
-__device__ __forceinline__ double t_exp(double x) { return exp(x); }
+// e^x for the covariance generation (x = -r <= 0): Cody and Waite's reduction
+// x = k ln 2 + f, k = rint(x / ln 2), |f| <= ln(2) / 2, with ln 2 split into a
+// 42-bit leading part (k ln2_hi is exact for |k| < 2^11) and the rest; then
+// e^f = 1 + (f + f^2 P(f)), P the Taylor series of (e^f - 1 - f) / f^2 to
+// degree 11 (truncation below 1e-17 relative), evaluated by Estrin's scheme:
+// the dependent chain is 6 operations deep against Horner's 13 (the
+// generation is latency-bound), and adding the 1 last keeps the error within
+// one ulp; finally scaled by 2^k.  x is clamped at -1000, where e^x is 0.
+__device__ __forceinline__ double t_exp(double x) {
+  x = fmax(x, -1000.0);
+  const double k = rint(x * 0x1.71547652b82fep+0);
+  double f = fma(-k, 0x1.62e42fefa3800p-1, x);
+  f = fma(-k, 0x1.ef35793c76730p-45, f);
+  const double f2 = f * f, f4 = f2 * f2, f8 = f4 * f4;
+  const double d0 = fma(f, 0x1.5555555555555p-3, 0x1.0000000000000p-1);
+  const double d1 = fma(f, 0x1.1111111111111p-7, 0x1.5555555555555p-5);
+  const double d2 = fma(f, 0x1.a01a01a01a01ap-13, 0x1.6c16c16c16c17p-10);
+  const double d3 = fma(f, 0x1.71de3a556c734p-19, 0x1.a01a01a01a01ap-16);
+  const double d4 = fma(f, 0x1.ae64567f544e4p-26, 0x1.27e4fb7789f5cp-22);
+  const double d5 = fma(f, 0x1.6124613a86d09p-33, 0x1.1eed8eff8d898p-29);
+  const double e0 = fma(d1, f2, d0), e1 = fma(d3, f2, d2), e2 = fma(d5, f2, d4);
+  const double p = fma(e2, f8, fma(e1, f4, e0));
+  return __builtin_amdgcn_ldexp(1.0 + fma(f2, p, f), (int)k);
+}
 __device__ __forceinline__ float t_exp(float x) { return expf(x); }
 __device__ __forceinline__ double t_sqrt(double x) { return sqrt(x); }
 __device__ __forceinline__ float t_sqrt(float x) { return sqrtf(x); }

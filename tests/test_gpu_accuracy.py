@@ -40,6 +40,30 @@ def test_covariance_kernel_matches_oracle(sbv):
         assert np.max(np.abs(same.cpu().numpy() - O.cov_matrix(Xa, Xa, th, two_nu, True))) < 1e-14
 
 
+def test_covariance_exp_within_two_ulps(sbv):
+    """nu = 1/2, d = 1, beta = sigma^2 = 1 between 0 and x: the device kernel
+    returns e^{-x}.  x = j / 1024 has an exact square, so the distance is x up
+    to one rounding of the square root; the exponential itself must stay
+    within two ulps of numpy's (Cody-Waite reduction, degree-13 Taylor series
+    in Estrin's form), into the subnormal range and to 0 beyond it."""
+    import torch
+    rng = np.random.default_rng(5)
+    j = np.r_[np.arange(0, 2048), rng.integers(0, 700 * 1024, 20000), [745 * 1024, 760 * 1024, 1000 * 1024]]
+    x = j / 1024.0
+    dev = torch.device("cuda:0")
+    out = torch.empty((1, len(x)), dtype=torch.float64, device=dev)
+    sbv.sbv_cov_matrix_dev(torch.zeros((1, 1), dtype=torch.float64, device=dev),
+                           torch.tensor(x[:, None], device=dev), torch.zeros(3, dtype=torch.float64, device=dev),
+                           1, out)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()[0]
+    ref = np.exp(-x)
+    normal = x <= 700
+    tol = 2 * np.spacing(ref[normal]) + ref[normal] * np.spacing(x[normal])
+    assert np.all(np.abs(got[normal] - ref[normal]) <= tol)
+    assert np.all(np.abs(got[~normal] - ref[~normal]) <= 1e-320)
+
+
 def test_kl_orderings_of_the_four_settings(sbv):
     n = 1500
     rng = np.random.default_rng(2)
