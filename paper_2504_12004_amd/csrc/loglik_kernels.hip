@@ -145,14 +145,17 @@ __device__ __forceinline__ int zld(int d) {
   return (d + ZV<T>::w - 1) / ZV<T>::w * ZV<T>::w;
 }
 
-// Matern correlation, closed forms of Eq. (maternkernel) for half-integer nu.
+// Matern correlation, closed forms of Eq. (maternkernel) for half-integer nu:
+// p(r) e^{-r} with p = 1, 1 + r, 1 + r + r^2/3, 1 + r + 2 r^2/5 + r^3/15 for
+// nu = 1/2, 3/2, 5/2, 7/2, taken as 1 + r (c1 + r (c2 + r c3)) with the
+// coefficients selected once from the (uniform) smoothness: no branch per
+// entry, so that the covariance generation can interleave its entries.
 template <typename T>
 __device__ __forceinline__ T matern(T r, int two_nu) {
-  T e = t_exp(-r);
-  if (two_nu == 5) return (T(1) + r + r * r * T(1.0 / 3.0)) * e;
-  if (two_nu == 3) return (T(1) + r) * e;
-  if (two_nu == 7) return (T(1) + r + r * r * T(0.4) + r * r * r * T(1.0 / 15.0)) * e;
-  return e;
+  const T c1 = two_nu >= 3 ? T(1) : T(0);
+  const T c2 = two_nu == 5 ? T(1.0 / 3.0) : (two_nu == 7 ? T(0.4) : T(0));
+  const T c3 = two_nu == 7 ? T(1.0 / 15.0) : T(0);
+  return fma(r, fma(r, fma(r, c3, c2), c1), T(1)) * t_exp(-r);
 }
 
 constexpr double kLog2Pi = 1.83787706640934548356065947281123527;
