@@ -497,14 +497,13 @@ __device__ __forceinline__ void gen_items(SM& sm, T* dst, const int (&e)[N], int
   for (int n = 0; n < N; ++n)
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-      T v;
-      if (pa[n][t] >= nA || pb[n] >= nA) {
-        v = (pa[n][t] == pb[n]) ? T(-1) : T(0);
-      } else {
-        v = -(sigma2 * matern<T>(g_sqrt(r2[n][t]), two_nu));
-        if (pa[n][t] == pb[n]) v -= tau2;
-      }
-      dst[256 * i[n] + 64 * t + l[n]] = v;
+      // padding rows and columns (beyond nA) take the identity; the entry is
+      // computed either way (from clamped points) and selected, so that no
+      // branch splits the straight-line code of the items
+      T v = -(sigma2 * matern<T>(g_sqrt(r2[n][t]), two_nu));
+      if (pa[n][t] == pb[n]) v -= tau2;
+      const T pad = (pa[n][t] == pb[n]) ? T(-1) : T(0);
+      dst[256 * i[n] + 64 * t + l[n]] = (pa[n][t] >= nA || pb[n] >= nA) ? pad : v;
     }
 }
 
@@ -573,12 +572,11 @@ __device__ __forceinline__ void gen_group(SM& sm, T* dst, int tid, int j0, int j
     }
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-      if (pa[t] >= nA || pb >= nA) {
-        v[t] = (pa[t] == pb) ? T(-1) : T(0);
-      } else {
-        v[t] = -(sigma2 * matern<T>(g_sqrt(r2[t]), two_nu));
-        if (pa[t] == pb) v[t] -= tau2;
-      }
+      // as in gen_items: computed from clamped points, padding selected
+      T c = -(sigma2 * matern<T>(g_sqrt(r2[t]), two_nu));
+      if (pa[t] == pb) c -= tau2;
+      const T pad = (pa[t] == pb) ? T(-1) : T(0);
+      v[t] = (pa[t] >= nA || pb >= nA) ? pad : c;
     }
   };
   int e = tid;
