@@ -348,6 +348,7 @@ def summarize_large(out, write_dir):
               f"{big['algorithmic_tflop_per_eval']:.3f} TFLOP algorithmic per evaluation, "
               f"{big['fp64']['total_algorithmic_tflops']:.2f} TFLOP/s = "
               f"{big['fp64']['total_algorithmic_tflops'] / 78.6:.3f} of the FP64 peak"]
+    os.makedirs(write_dir, exist_ok=True)
     with open(os.path.join(write_dir, "k_block_large_m400_5m.md"), "w") as f:
         f.write("\n".join(L) + "\n")
     with open(os.path.join(write_dir, "k_block_large_m400_5m.json"), "w") as f:
