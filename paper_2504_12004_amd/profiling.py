@@ -270,9 +270,9 @@ def summarize_large(out, write_dir):
     def kind(name):
         if "k_block_prefix<double" in name:
             return "prefix"
-        if "k_block_loglik<double, 17, 8, false, false, false, true>" in name:
+        if "k_block_loglik<double, 17, 8, false, false, false, true" in name:
             return "trailing"
-        if "k_block_loglik<double, 17, 8, true, false, false, true>" in name:
+        if "k_block_loglik<double, 17, 8, true, false, false, true" in name:
             return "trailing_grad"
         return None
     empty_ns = 50e3
